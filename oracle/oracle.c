@@ -299,11 +299,17 @@ static void eval_node(const orc_model* m, int id, const double* xe,
       return;
     }
     case ORC_SUM: {
-      /* P = f A + (1 - f) B */
+      /* P = f A + (1 - f) B, a density only for 0 <= f <= 1 */
       val_t* A = (val_t*)malloc(sizeof(val_t));
       val_t* B = (val_t*)malloc(sizeof(val_t));
       int pf = nd->par[0];
       double f = th[pf];
+      if (!(f >= 0.0 && f <= 1.0)) { /* not a mixture of densities */
+        o->v = NAN;
+        free(A);
+        free(B);
+        return;
+      }
       eval_node(m, nd->child[0], xe, th, order, A);
       eval_node(m, nd->child[1], xe, th, order, B);
       o->v = f * A->v + (1.0 - f) * B->v;

@@ -28,7 +28,8 @@ enum {
   ORC_PWAVE = 4, /* P-wave density in dim = {ctl, ctk, phi};
                     par = {FL, S3, S4, S5, AFB, S7, S8, S9}             (Eq. 4) */
   ORC_PROD = 5,  /* product of children over disjoint dimensions               */
-  ORC_SUM = 6    /* f*child[0] + (1-f)*child[1]; par = {f}                     */
+  ORC_SUM = 6    /* f*child[0] + (1-f)*child[1]; par = {f}; f outside [0,1]
+                    is outside the model's domain (P treated as non-finite)   */
 };
 
 /* One node: 18 ints in this order (the layout the Python wrapper writes). */

@@ -416,3 +416,14 @@ def test_nonpositive_density_gives_infinite_nll_and_count():
     assert bad > 0 and nll == math.inf and np.all(g == 0)
     p = m.pdf(x, th)
     assert bad == int(np.sum(~(p > 0)))
+
+
+def test_fraction_outside_unit_interval_is_outside_the_domain():
+    m = oracle.Model(W.mass1d())
+    x = G.gen_mass1d(100, 4)
+    for f in (-0.01, 1.2):
+        nll, _, _, bad = m.nll(x, np.array([5.28, 0.02, -1.5, f]), order=1)
+        assert nll == math.inf and bad == 100
+    for f in (0.0, 1.0):   # the closed ends are valid mixtures
+        nll, _, _, bad = m.nll(x, np.array([5.28, 0.02, -1.5, f]))
+        assert bad == 0 and math.isfinite(nll)
