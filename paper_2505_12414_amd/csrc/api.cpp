@@ -1,0 +1,301 @@
+// extern "C" entry points of libuml: models, event data and evaluation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host.h"
+
+namespace uml {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace uml
+
+using namespace uml;
+
+extern "C" {
+
+const char* uml_last_error(void) { return g_err.c_str(); }
+const char* uml_version(void) { return UML_VERSION_STRING; }
+
+int uml_model_create(const uml_model_desc* desc, uml_model** out) {
+  if (!out) return set_error(UML_E_INVALID, "uml_model_create: out is NULL");
+  *out = nullptr;
+  uml_model* m = new (std::nothrow) uml_model();
+  if (!m) return set_error(UML_E_NOMEM, "uml_model_create: out of host memory");
+  std::string err;
+  int rc = build_plan(desc, m->plan, err);
+  if (rc != UML_OK) {
+    delete m;
+    return set_error(rc, "uml_model_create: " + err);
+  }
+  const std::string sig = plan_signature(m->plan);
+  m->family = find_family(sig);
+  if (!m->family) {
+    delete m;
+    return set_error(UML_E_UNSUPPORTED, "uml_model_create: no compiled kernel for model shape '" +
+                                            sig + "' (compiled: " + family_list() + ")");
+  }
+  if (m->family->K != m->plan.K || m->family->ncst != m->plan.ncst) {
+    delete m;
+    return set_error(UML_E_INVALID, "uml_model_create: internal layout mismatch for " + sig);
+  }
+  hipError_t e = hipGetDevice(&m->device);
+  if (e == hipSuccess) e = hipMalloc(&m->d_plan, sizeof(Plan));
+  if (e == hipSuccess) e = hipMemcpy(m->d_plan, &m->plan, sizeof(Plan), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (m->d_plan) (void)hipFree(m->d_plan);
+    delete m;
+    return set_error(UML_E_HIP, std::string("uml_model_create: ") + hipGetErrorString(e));
+  }
+  *out = m;
+  return UML_OK;
+}
+
+void uml_model_destroy(uml_model* m) {
+  if (!m) return;
+  if (m->d_plan) (void)hipFree(m->d_plan);
+  delete m;
+}
+
+int uml_model_n_free(const uml_model* m) { return m ? m->plan.nfree : UML_E_INVALID; }
+
+int uml_model_describe(const uml_model* m, char* buf, int32_t len) {
+  if (!m || !buf || len <= 0) return set_error(UML_E_INVALID, "uml_model_describe: bad argument");
+  std::string s = plan_describe(m->plan);
+  std::strncpy(buf, s.c_str(), size_t(len) - 1);
+  buf[len - 1] = 0;
+  return UML_OK;
+}
+
+int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int32_t dtype,
+                    const void* w, int32_t flags, void* stream, uml_data** out) {
+  if (!out) return set_error(UML_E_INVALID, "uml_data_create: out is NULL");
+  *out = nullptr;
+  if (!m) return set_error(UML_E_INVALID, "uml_data_create: model is NULL");
+  if (n < 0) return set_error(UML_E_INVALID, "uml_data_create: negative event count");
+  if (dtype != UML_F32 && dtype != UML_F64)
+    return set_error(UML_E_INVALID, "uml_data_create: dtype must be UML_F32 or UML_F64");
+  const Plan& P = m->plan;
+  if (n > 0 && !cols) return set_error(UML_E_INVALID, "uml_data_create: cols is NULL");
+  if (n > 0)
+    for (int ud = 0; ud < P.ndim; ++ud)
+      if (!cols[ud]) return set_error(UML_E_INVALID, "uml_data_create: column pointer is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool mixed = P.precision == UML_MIXED;
+  const size_t esz = mixed ? 4 : 8;     // storage element
+  const size_t ssz = dtype == UML_F32 ? 4 : 8;  // source element
+
+  // gather the source on the host (device sources are copied back first)
+  std::vector<char> hsrc;
+  std::vector<const void*> src(P.ndim + 1, nullptr);
+  if (n > 0) {
+    if (flags & UML_DATA_DEVICE_SRC) {
+      hsrc.resize(size_t(n) * ssz * (P.ndim + (w ? 1 : 0)));
+      for (int ud = 0; ud < P.ndim; ++ud) {
+        UML_HIP_CHECK(hipMemcpy(hsrc.data() + size_t(ud) * n * ssz, cols[ud], n * ssz,
+                                hipMemcpyDeviceToHost));
+        src[ud] = hsrc.data() + size_t(ud) * n * ssz;
+      }
+      if (w) {
+        UML_HIP_CHECK(hipMemcpy(hsrc.data() + size_t(P.ndim) * n * ssz, w, n * ssz,
+                                hipMemcpyDeviceToHost));
+        src[P.ndim] = hsrc.data() + size_t(P.ndim) * n * ssz;
+      }
+    } else {
+      for (int ud = 0; ud < P.ndim; ++ud) src[ud] = cols[ud];
+      src[P.ndim] = w;
+    }
+  }
+
+  // convert into kernel-dimension order and storage type, validating ranges
+  const int ncols = P.ndim + (w ? 1 : 0);
+  const int64_t stride = align_up(std::max<int64_t>(n, 1), 64);  // elements per column
+  std::vector<char> host(size_t(stride) * esz * ncols, 0);
+  for (int kd = 0; kd < ncols; ++kd) {
+    const bool is_w = kd == P.ndim;
+    const int ud = is_w ? -1 : P.user_of_dim[kd];
+    const void* sp = is_w ? src[P.ndim] : src[ud];
+    const double lo = is_w ? 0 : P.lo[kd], hi = is_w ? 0 : P.hi[kd];
+    char* dst = host.data() + size_t(kd) * stride * esz;
+    for (int64_t i = 0; i < n; ++i) {
+      double v = dtype == UML_F32 ? double(static_cast<const float*>(sp)[i])
+                                  : static_cast<const double*>(sp)[i];
+      double stored = mixed ? double(float(v)) : v;
+      if (is_w) {
+        if (!std::isfinite(stored))
+          return set_error(UML_E_EVENT_DOMAIN, "uml_data_create: weight " + std::to_string(i) +
+                                                   " is not finite");
+      } else if (!(stored >= lo && stored <= hi)) {
+        return set_error(UML_E_EVENT_DOMAIN,
+                         "uml_data_create: event " + std::to_string(i) + " dimension " +
+                             std::to_string(ud) + " value " + std::to_string(v) +
+                             " is outside [" + std::to_string(lo) + ", " + std::to_string(hi) +
+                             "] or NaN" + (mixed ? " (after rounding to FP32)" : ""));
+      }
+      if (mixed)
+        reinterpret_cast<float*>(dst)[i] = float(stored);
+      else
+        reinterpret_cast<double*>(dst)[i] = stored;
+    }
+  }
+
+  uml_data* d = new (std::nothrow) uml_data();
+  if (!d) return set_error(UML_E_NOMEM, "uml_data_create: out of host memory");
+  d->model = m;
+  d->n = n;
+  d->weighted = w ? 1 : 0;
+  d->E = events_per_thread(n, P.precision);
+  const int64_t tsize = int64_t(d->E) * kBlock;
+  d->n_tiles = int(std::max<int64_t>(1, (n + tsize - 1) / tsize));
+  d->bytes_events = int64_t(host.size());
+
+  // work area: job | constants | theta | out | counter | partials
+  const int64_t o_job = 0;
+  const int64_t o_cst = align_up(o_job + sizeof(Job), 256);
+  const int64_t o_theta = align_up(o_cst + sizeof(ConstBlock), 256);
+  const int64_t o_out = align_up(o_theta + sizeof(double) * UML_MAX_PARAMS, 256);
+  const int64_t o_cnt = align_up(o_out + sizeof(double) * (1 + UML_MAX_PARAMS), 256);
+  const int64_t o_part = align_up(o_cnt + 256, 256);
+  d->bytes_work = o_part + int64_t(sizeof(double)) * P.K * d->n_tiles;
+
+  auto fail = [&](hipError_t e, const char* what) {
+    if (d->d_events) (void)hipFree(d->d_events);
+    if (d->d_work) (void)hipFree(d->d_work);
+    if (d->h_stage) (void)hipHostFree(d->h_stage);
+    delete d;
+    return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
+                     std::string("uml_data_create: ") + what + ": " + hipGetErrorString(e));
+  };
+  hipError_t e = hipMalloc(&d->d_events, host.size());
+  if (e != hipSuccess) return fail(e, "event buffer");
+  e = hipMalloc(&d->d_work, d->bytes_work);
+  if (e != hipSuccess) return fail(e, "work buffer");
+  e = hipHostMalloc(reinterpret_cast<void**>(&d->h_stage), sizeof(double) * 4 * (UML_MAX_PARAMS + 2),
+                    hipHostMallocDefault);
+  if (e != hipSuccess) return fail(e, "pinned staging");
+  char* wbase = static_cast<char*>(d->d_work);
+  d->d_job = reinterpret_cast<Job*>(wbase + o_job);
+  d->d_theta = reinterpret_cast<double*>(wbase + o_theta);
+  d->d_out = reinterpret_cast<double*>(wbase + o_out);
+  Job& J = d->job;
+  std::memset(&J, 0, sizeof(J));
+  for (int kd = 0; kd < P.ndim; ++kd)
+    J.col[kd] = static_cast<char*>(d->d_events) + size_t(kd) * stride * esz;
+  J.w = w ? static_cast<char*>(d->d_events) + size_t(P.ndim) * stride * esz : nullptr;
+  J.n = n;
+  J.n_tiles = d->n_tiles;
+  J.events_per_thread = d->E;
+  J.cst = reinterpret_cast<ConstBlock*>(wbase + o_cst);
+  J.partials = reinterpret_cast<double*>(wbase + o_part);
+  J.counter = reinterpret_cast<unsigned int*>(wbase + o_cnt);
+  J.out = d->d_out;
+  J.plan = m->d_plan;
+  J.fit = nullptr;
+  J.theta = d->d_theta;
+  e = hipMemcpyAsync(d->d_events, host.data(), host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(wbase, 0, o_part, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(e, "upload");
+  *out = d;
+  return UML_OK;
+}
+
+void uml_data_destroy(uml_data* d) {
+  if (!d) return;
+  if (d->d_events) (void)hipFree(d->d_events);
+  if (d->d_work) (void)hipFree(d->d_work);
+  if (d->d_hess_part) (void)hipFree(d->d_hess_part);
+  if (d->h_stage) (void)hipHostFree(d->h_stage);
+  delete d;
+}
+
+int64_t uml_data_n_events(const uml_data* d) { return d ? d->n : UML_E_INVALID; }
+
+}  // extern "C"
+
+namespace uml {
+
+static int check_pair(const uml_model* m, const uml_data* d, const char* fn) {
+  if (!m || !d) return set_error(UML_E_INVALID, std::string(fn) + ": null handle");
+  if (d->model != m)
+    return set_error(UML_E_INVALID, std::string(fn) + ": data was created for another model");
+  return UML_OK;
+}
+
+// Queues the event kernel for one dataset (one launch per evaluation).
+static int queue_eval(const uml_model* m, const uml_data* d, const double* d_theta, double* d_out,
+                      hipStream_t s) {
+  LaunchArgs a{};
+  a.jobs = d->d_job;
+  a.tmap = nullptr;
+  a.grid = d->n_tiles;
+  a.out = d_out;
+  a.theta = d_theta;
+  a.precision = m->plan.precision;
+  a.stream = s;
+  m->family->eval(a);
+  UML_HIP_CHECK(hipGetLastError());
+  return UML_OK;
+}
+
+static int eval_host(const uml_model* m, const uml_data* d, const double* theta, double* nll,
+                     double* grad, void* stream, const char* fn) {
+  int rc = check_pair(m, d, fn);
+  if (rc) return rc;
+  if (!theta || !nll) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+  const Plan& P = m->plan;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* hs = d->h_stage;
+  std::memcpy(hs, theta, sizeof(double) * P.npar);
+  UML_HIP_CHECK(hipMemcpyAsync(d->d_theta, hs, sizeof(double) * P.npar, hipMemcpyHostToDevice, s));
+  rc = queue_eval(m, d, nullptr, nullptr, s);
+  if (rc) return rc;
+  double* ho = hs + UML_MAX_PARAMS;
+  UML_HIP_CHECK(hipMemcpyAsync(ho, d->d_out, sizeof(double) * (1 + P.nfree), hipMemcpyDeviceToHost, s));
+  UML_HIP_CHECK(hipStreamSynchronize(s));
+  *nll = ho[0];
+  if (grad) std::memcpy(grad, ho + 1, sizeof(double) * P.nfree);
+  if (!std::isfinite(ho[0]))
+    return set_error(UML_E_PDF_NONPOSITIVE,
+                     std::string(fn) + ": P <= 0 or non-finite at some event, or parameters "
+                     "outside the model's domain");
+  return UML_OK;
+}
+
+}  // namespace uml
+
+extern "C" {
+
+int uml_eval_nll(const uml_model* m, const uml_data* d, const double* theta_all, double* nll,
+                 void* stream) {
+  return eval_host(m, d, theta_all, nll, nullptr, stream, "uml_eval_nll");
+}
+
+int uml_eval_nll_grad(const uml_model* m, const uml_data* d, const double* theta_all,
+                      double* nll, double* grad_free, void* stream) {
+  return eval_host(m, d, theta_all, nll, grad_free, stream, "uml_eval_nll_grad");
+}
+
+int uml_eval_nll_grad_dev(const uml_model* m, const uml_data* d, const double* d_theta_all,
+                          double* d_out, void* stream) {
+  int rc = check_pair(m, d, "uml_eval_nll_grad_dev");
+  if (rc) return rc;
+  if (!d_theta_all || !d_out)
+    return set_error(UML_E_INVALID, "uml_eval_nll_grad_dev: null device pointer");
+  return queue_eval(m, d, d_theta_all, d_out, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,829 @@
+// Event kernels of libuml for gfx950.
+//
+// One launch evaluates -sum_i w_i ln P(x_i|theta) (Eq. 1) and every sum the
+// gradient needs, for one dataset or for many (one "job" each):
+//   * each workgroup owns one fixed-size tile of one job's events; each lane
+//     reads its events as 16-byte vectors from the structure-of-arrays columns,
+//     computes the mixture in base-2 log space and accumulates the K moment
+//     sums in registers (FP32 in mixed mode, FP64 otherwise);
+//   * the workgroup reduces its lanes through LDS in a fixed order and writes
+//     one FP64 partial per moment and tile (pass 1);
+//   * the last workgroup of a job to finish (an integer atomic counter) sums
+//     the tile partials in tile order with Neumaier compensation (pass 2) and
+//     assembles NLL and gradient in FP64 (epilogue).
+// No floating-point atomics: results are bitwise reproducible and independent
+// of the grid, because a tile's lanes, its reduction order and the tile size
+// depend only on the job's own event count.
+//
+// The parameter-only terms (normalisation integrals, the combined prefactors
+// of Eq. 3, the angular coefficients) are computed once per parameter point by
+// the prologue kernel in FP64 and rounded to FP32 for mixed mode.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <type_traits>
+#include <utility>
+
+#include "kernels.h"
+#include "uml_internal.h"
+
+namespace uml {
+
+// ---------------------------------------------------------------------------
+// compile-time helpers
+// ---------------------------------------------------------------------------
+
+template <int I, class... Ts>
+struct TypeAt;
+template <class T, class... Ts>
+struct TypeAt<0, T, Ts...> {
+  using type = T;
+};
+template <int I, class T, class... Ts>
+struct TypeAt<I, T, Ts...> {
+  using type = typename TypeAt<I - 1, Ts...>::type;
+};
+
+template <class Fn, int... Is>
+__host__ __device__ __forceinline__ void sfor_impl(Fn&& fn, std::integer_sequence<int, Is...>) {
+  (fn(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class Fn>
+__host__ __device__ __forceinline__ void sfor(Fn&& fn) {
+  sfor_impl(fn, std::make_integer_sequence<int, N>{});
+}
+
+// ---------------------------------------------------------------------------
+// arithmetic of the two precisions
+// ---------------------------------------------------------------------------
+
+// FP32: single hardware instructions (v_exp_f32, v_log_f32, v_rcp_f32,
+// v_sqrt_f32, v_sin_f32, v_cos_f32), each correct to about one ulp.
+__device__ __forceinline__ float k_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float k_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float k_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float k_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ void k_sincos(float phi, float& s, float& c) {
+  // the hardware sine and cosine take their argument in revolutions
+  const float t = phi * 0.15915494309189535f;
+  s = __builtin_amdgcn_sinf(t);
+  c = __builtin_amdgcn_cosf(t);
+}
+// FP64: the device math library.
+__device__ __forceinline__ double k_exp2(double x) { return exp2(x); }
+__device__ __forceinline__ double k_log2(double x) { return log2(x); }
+__device__ __forceinline__ double k_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double k_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ void k_sincos(double phi, double& s, double& c) { sincos(phi, &s, &c); }
+
+struct PrecMixed {
+  using T = float;
+  static constexpr int VW = 4;  // one 16-byte load = 4 events
+  __device__ static const float* consts(const ConstBlock* cb) { return cb->f; }
+  __device__ static const float* xrefs(const ConstBlock* cb) { return cb->xf; }
+};
+struct PrecF64 {
+  using T = double;
+  static constexpr int VW = 2;
+  __device__ static const double* consts(const ConstBlock* cb) { return cb->d; }
+  __device__ static const double* xrefs(const ConstBlock* cb) { return cb->xd; }
+};
+
+// ---------------------------------------------------------------------------
+// catalogue factors: per-event value and moments
+//   exp-type factors add to the component's base-2 exponent e,
+//   polynomial-type factors return their value v;
+//   m[] receives the event-dependent factors of the moment sums.
+// Kernel constants c[] are written by the prologue (see compute_constants).
+// ---------------------------------------------------------------------------
+
+// Gaussian in dimension D.  c = {mu - xref, log2(e) / (2 sigma^2)}.
+template <int D>
+struct Gauss {
+  static constexpr int kind = FK_GAUSS, order = 0;
+  static constexpr int ncst = fk_ncst(FK_GAUSS, 0), nmom = fk_nmom(FK_GAUSS, 0);
+  static constexpr bool expo = true;
+  static constexpr int maxdim = D;
+  static constexpr unsigned shift_mask = 1u << D;
+  static std::string sig() { return "G" + std::to_string(D); }
+  template <class T>
+  __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
+    const T d = xs[D] - c[0];
+    const T d2 = d * d;
+    e = fma(-d2, c[1], e);
+    m[0] = d;
+    m[1] = d2;
+    (void)v;
+  }
+};
+
+// Exponential e^{lambda x} in dimension D.  c = {lambda log2(e)}.
+template <int D>
+struct Exp {
+  static constexpr int kind = FK_EXP, order = 0;
+  static constexpr int ncst = fk_ncst(FK_EXP, 0), nmom = fk_nmom(FK_EXP, 0);
+  static constexpr bool expo = true;
+  static constexpr int maxdim = D;
+  static constexpr unsigned shift_mask = 1u << D;
+  static std::string sig() { return "E" + std::to_string(D); }
+  template <class T>
+  __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
+    e = fma(xs[D], c[0], e);
+    m[0] = xs[D];
+    (void)v;
+  }
+};
+
+// Chebyshev series of order N in dimension D, normalised:
+// v = (1 + sum c_j T_j(u)) / N_C.  c = {s, t, 1/N_C, c_1/N_C .. c_N/N_C}, u = x s + t.
+template <int D, int N>
+struct Cheb {
+  static constexpr int kind = FK_CHEB, order = N;
+  static constexpr int ncst = fk_ncst(FK_CHEB, N), nmom = fk_nmom(FK_CHEB, N);
+  static constexpr bool expo = false;
+  static constexpr int maxdim = D;
+  static constexpr unsigned shift_mask = 0;
+  static std::string sig() { return "C" + std::to_string(D) + "." + std::to_string(N); }
+  template <class T>
+  __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
+    const T u = fma(xs[D], c[0], c[1]);
+    T tj[N + 1];
+    tj[0] = T(1);
+    tj[1] = u;
+    if constexpr (N >= 2) {
+      const T u2 = u + u;
+#pragma unroll
+      for (int j = 2; j <= N; ++j) tj[j] = fma(u2, tj[j - 1], -tj[j - 2]);
+    }
+    T val = c[2];
+#pragma unroll
+    for (int j = 1; j <= N; ++j) {
+      val = fma(c[2 + j], tj[j], val);
+      m[j - 1] = tj[j];
+    }
+    v = val;
+    (void)e;
+  }
+};
+
+// P-wave angular density (Eq. 4) in dimensions (cos theta_l, cos theta_K, phi).
+// Written as  v = c0 u0 + c1 (u1 - u0) + sum_k c_{k+1} b_k  with
+//   u0 = sin^2 K (3/4 + cos 2l / 4),  u1 = cos^2 K (1 - cos 2l),
+//   b = {S3, S4, S5, AFB, S7, S8, S9 terms},
+// c = 9/(32 pi) * {1, FL, S3, S4, S5, AFB, S7, S8, S9};
+// moments m = {u1 - u0, b_S3, .., b_S9}.
+template <int D0, int D1, int D2>
+struct PWave {
+  static constexpr int kind = FK_PWAVE, order = 0;
+  static constexpr int ncst = fk_ncst(FK_PWAVE, 0), nmom = fk_nmom(FK_PWAVE, 0);
+  static constexpr bool expo = false;
+  static constexpr int maxdim = D0 > D1 ? (D0 > D2 ? D0 : D2) : (D1 > D2 ? D1 : D2);
+  static constexpr unsigned shift_mask = 0;
+  static std::string sig() {
+    return "P" + std::to_string(D0) + std::to_string(D1) + std::to_string(D2);
+  }
+  template <class T>
+  __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
+    const T cl = xs[D0], ck = xs[D1], ph = xs[D2];
+    const T sl2 = (T(1) - cl) * (T(1) + cl);  // sin^2 theta_l
+    const T sk2 = (T(1) - ck) * (T(1) + ck);  // sin^2 theta_K
+    const T sl = k_sqrt(sl2), sk = k_sqrt(sk2);
+    T sp, cp;
+    k_sincos(ph, sp, cp);
+    const T u0 = sk2 * fma(T(-0.5), sl2, T(1));
+    const T u1 = T(2) * ck * ck * sl2;
+    const T skl2 = sk2 * sl2;
+    const T s2k_sl = T(2) * sk * ck * sl;        // sin 2K sin l
+    const T s2k_s2l = T(2) * s2k_sl * cl;        // sin 2K sin 2l
+    m[0] = u1 - u0;
+    m[1] = skl2 * ((cp - sp) * (cp + sp));       // S3: sin^2K sin^2l cos 2phi
+    m[2] = s2k_s2l * cp;                         // S4
+    m[3] = s2k_sl * cp;                          // S5
+    m[4] = T(4.0 / 3.0) * sk2 * cl;              // AFB
+    m[5] = s2k_sl * sp;                          // S7
+    m[6] = s2k_s2l * sp;                         // S8
+    m[7] = skl2 * (T(2) * sp * cp);              // S9: sin^2K sin^2l sin 2phi
+    T val = c[0] * u0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) val = fma(c[1 + k], m[k], val);
+    v = val;
+    (void)e;
+  }
+};
+
+template <class... F>
+struct Comp {
+  static constexpr int nfac = sizeof...(F);
+  static constexpr int ncst = 1 + (F::ncst + ... + 0);
+  static constexpr int nmom = 1 + (F::nmom + ... + 0);
+  static constexpr int maxdim = std::max({F::maxdim...});
+  static constexpr unsigned shift_mask = (F::shift_mask | ... | 0u);
+  template <int I>
+  using fac = typename TypeAt<I, F...>::type;
+  // offsets inside the component's block: constants after log2 K_c,
+  // moments after r_c
+  static constexpr int cst_off(int i) {
+    constexpr int a[] = {F::ncst...};
+    int o = 1;
+    for (int k = 0; k < i; ++k) o += a[k];
+    return o;
+  }
+  static constexpr int mom_off(int i) {
+    constexpr int a[] = {F::nmom...};
+    int o = 1;
+    for (int k = 0; k < i; ++k) o += a[k];
+    return o;
+  }
+  static std::string sig() { return (std::string() + ... + F::sig()); }
+};
+
+template <class... C>
+struct Shape {
+  static constexpr int ncomp = sizeof...(C);
+  static constexpr int K = 1 + (C::nmom + ...);
+  static constexpr int ncst = (C::ncst + ...);
+  static constexpr int ndim = std::max({C::maxdim...}) + 1;
+  static constexpr unsigned shift_mask = (C::shift_mask | ...);
+  template <int I>
+  using comp = typename TypeAt<I, C...>::type;
+  static constexpr int cst_base(int i) {
+    constexpr int a[] = {C::ncst...};
+    int o = 0;
+    for (int k = 0; k < i; ++k) o += a[k];
+    return o;
+  }
+  static constexpr int mom_base(int i) {  // slot of r_c
+    constexpr int a[] = {C::nmom...};
+    int o = 1;
+    for (int k = 0; k < i; ++k) o += a[k];
+    return o;
+  }
+  static std::string sig() {
+    std::string s;
+    ((s += (s.empty() ? "" : "|") + C::sig()), ...);
+    return s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// one event
+// ---------------------------------------------------------------------------
+
+template <class S, class T, bool W>
+__device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S::ncst],
+                                      const T (&xref)[S::ndim], T (&acc)[S::K]) {
+  constexpr int NC = S::ncomp;
+  T xs[S::ndim];
+  sfor<S::ndim>([&](auto Id) {
+    constexpr int d = Id;
+    if constexpr ((S::shift_mask >> d) & 1u)
+      xs[d] = x[d] - xref[d];  // exact in FP32 for x within [xref/2, 2 xref]
+    else
+      xs[d] = x[d];
+  });
+  T E[NC], V[NC], mom[S::K];
+  T pv[NC][kMaxFacPerComp];
+  sfor<NC>([&](auto Ic) {
+    constexpr int ci = Ic;
+    using Cc = typename S::template comp<ci>;
+    constexpr int cb = S::cst_base(ci), mb = S::mom_base(ci);
+    T e = c[cb];  // log2 K_c
+    T v = T(1);
+    sfor<Cc::nfac>([&](auto If) {
+      constexpr int fi = If;
+      using Fc = typename Cc::template fac<fi>;
+      T pval = T(1);
+      Fc::template eval<T>(xs, c + cb + Cc::cst_off(fi), e, pval, mom + mb + Cc::mom_off(fi));
+      pv[ci][fi] = pval;
+      if constexpr (!Fc::expo) v *= pval;
+    });
+    E[ci] = e;
+    V[ci] = v;
+  });
+  // P = 2^Emax sum_c 2^{E_c - Emax} V_c
+  T ec[NC], Emax;
+  if constexpr (NC == 1) {
+    ec[0] = T(1);
+    Emax = E[0];
+  } else if constexpr (NC == 2) {
+    const T dE = E[0] - E[1];
+    const T t = k_exp2(-fabs(dE));
+    const bool ge = dE >= T(0);
+    ec[0] = ge ? T(1) : t;
+    ec[1] = ge ? t : T(1);
+    Emax = ge ? E[0] : E[1];
+  } else {
+    Emax = E[0];
+#pragma unroll
+    for (int i = 1; i < NC; ++i) Emax = fmax(Emax, E[i]);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) ec[i] = k_exp2(E[i] - Emax);
+  }
+  T Sp[NC], sum = T(0);
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    Sp[i] = ec[i] * V[i];
+    sum += Sp[i];
+  }
+  const T l2 = Emax + k_log2(sum);  // log2 P
+  const T inv = k_rcp(sum);
+  acc[0] += W ? w * l2 : l2;
+  sfor<NC>([&](auto Ic) {
+    constexpr int ci = Ic;
+    using Cc = typename S::template comp<ci>;
+    constexpr int mb = S::mom_base(ci);
+    const T r = Sp[ci] * inv;
+    const T wr = W ? w * r : r;
+    acc[mb] += wr;
+    const T wq = (W ? w * ec[ci] : ec[ci]) * inv;  // r_c / V_c
+    sfor<Cc::nfac>([&](auto If) {
+      constexpr int fi = If;
+      using Fc = typename Cc::template fac<fi>;
+      constexpr int o = mb + Cc::mom_off(fi);
+      if constexpr (Fc::expo) {
+#pragma unroll
+        for (int k = 0; k < Fc::nmom; ++k) acc[o + k] = fma(wr, mom[o + k], acc[o + k]);
+      } else {
+        T q = wq;  // r_c / v_f = wq * prod of the component's other polynomial factors
+        sfor<Cc::nfac>([&](auto Ig) {
+          constexpr int gi = Ig;
+          using Gc = typename Cc::template fac<gi>;
+          if constexpr (gi != fi && !Gc::expo) q *= pv[ci][gi];
+        });
+#pragma unroll
+        for (int k = 0; k < Fc::nmom; ++k) acc[o + k] = fma(q, mom[o + k], acc[o + k]);
+      }
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// one tile
+// ---------------------------------------------------------------------------
+
+template <class T, int VW>
+struct Vec;
+template <>
+struct Vec<float, 4> {
+  using type = float4;
+};
+template <>
+struct Vec<double, 2> {
+  using type = double2;
+};
+
+template <class T, int VW>
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&out)[VW]) {
+  using V = typename Vec<T, VW>::type;
+  const V v = *reinterpret_cast<const V*>(p);
+  if constexpr (VW == 4) {
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  } else {
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+}
+
+template <class S, class P, bool W, bool FULL>
+__device__ __forceinline__ void process_tile(const Job& J, int64_t base,
+                                             const typename P::T (&c)[S::ncst],
+                                             const typename P::T (&xref)[S::ndim],
+                                             typename P::T (&acc)[S::K]) {
+  using T = typename P::T;
+  constexpr int VW = P::VW;
+  const int groups = J.events_per_thread / VW;
+  const int64_t n = J.n;
+  const T* __restrict__ col[S::ndim];
+#pragma unroll
+  for (int d = 0; d < S::ndim; ++d) col[d] = static_cast<const T*>(J.col[d]);
+  const T* __restrict__ wcol = static_cast<const T*>(J.w);
+  for (int g = 0; g < groups; ++g) {
+    const int64_t e0 = base + int64_t(g) * (VW * kBlock) + int64_t(VW) * threadIdx.x;
+    T xv[VW][S::ndim];
+    T wv[VW];
+    if constexpr (FULL) {
+#pragma unroll
+      for (int d = 0; d < S::ndim; ++d) {
+        T tmp[VW];
+        load_vec<T, VW>(col[d] + e0, tmp);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) xv[q][d] = tmp[q];
+      }
+      if constexpr (W) load_vec<T, VW>(wcol + e0, wv);
+    } else {
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        const bool ok = e0 + q < n;
+#pragma unroll
+        for (int d = 0; d < S::ndim; ++d) xv[q][d] = ok ? col[d][e0 + q] : T(0);
+        if constexpr (W) wv[q] = ok ? wcol[e0 + q] : T(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < VW; ++q) {
+      if (FULL || e0 + q < n) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, acc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prologue and epilogue (FP64, one lane)
+// ---------------------------------------------------------------------------
+
+// The FP64 library functions are called, not inlined, from the once-per-point
+// code below: the event kernels' register budget is the maximum over every
+// function they can reach, and the event loop must not pay for erfc.
+__device__ __noinline__ double nl_erfc(double x) { return erfc(x); }
+__device__ __noinline__ double nl_exp(double x) { return exp(x); }
+__device__ __noinline__ double nl_log(double x) { return log(x); }
+__device__ __noinline__ double nl_log2(double x) { return log2(x); }
+__device__ __noinline__ double nl_expm1(double x) { return expm1(x); }
+
+// Phi(zb) - Phi(za), za < zb, with erfc where both share a sign.
+__device__ __noinline__ double d_phi_diff(double za, double zb) {
+  const double r = 0.70710678118654752440;
+  if (za >= 0.0) return 0.5 * (nl_erfc(za * r) - nl_erfc(zb * r));
+  if (zb <= 0.0) return 0.5 * (nl_erfc(-zb * r) - nl_erfc(-za * r));
+  return 1.0 - 0.5 * nl_erfc(zb * r) - 0.5 * nl_erfc(-za * r);
+}
+
+// Mean offset of a truncated exponential: E[x] - a = L * h(lambda L),
+// h(z) = 1/(1 - e^{-z}) - 1/z, by its Taylor series near z = 0.
+__device__ __noinline__ double d_exp_h(double z) {
+  if (fabs(z) < 0.05) {
+    const double z2 = z * z;
+    return 0.5 + z * (1.0 / 12.0 + z2 * (-1.0 / 720.0 + z2 * (1.0 / 30240.0 - z2 / 1209600.0)));
+  }
+  return -1.0 / nl_expm1(-z) - 1.0 / z;
+}
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kSqrt2Pi = 2.5066282746310005024;
+
+// Gaussian normalised on [a, b] (Eq. 2): constants of the kernel, epilogue
+// derivatives of its log-normalisation, and log2 of its prefactor
+// 1 / (sigma sqrt(2 pi) (Phi(zb) - Phi(za))).
+__device__ __noinline__ bool gauss_constants(const FactorPlan& F, const double* __restrict__ th,
+                                             double* kc, double* ec, double* lnorm2) {
+  const double a = F.lo[0], b = F.hi[0];
+  const double mu = th[F.par[0]], sg = th[F.par[1]];
+  const double za = (a - mu) / sg, zb = (b - mu) / sg;
+  const double D = d_phi_diff(za, zb);
+  const double pa = nl_exp(-0.5 * za * za) / kSqrt2Pi, pb = nl_exp(-0.5 * zb * zb) / kSqrt2Pi;
+  kc[0] = mu - F.xref;
+  kc[1] = kLog2e / (2.0 * sg * sg);
+  *lnorm2 = -nl_log2(sg * kSqrt2Pi * D);
+  ec[0] = 1.0 / (sg * sg);                              // d ln g / d mu = d/sigma^2 - ec[1]
+  ec[1] = (pa - pb) / (sg * D);
+  ec[2] = 1.0 / (sg * sg * sg);                         // d ln g / d sigma = d^2/sigma^3 - ec[3]
+  ec[3] = 1.0 / sg + (za * pa - zb * pb) / (sg * D);
+  return sg > 0.0;
+}
+
+// Exponential e^{lambda x} normalised on [a, b] (Eq. 2), evaluated as
+// 2^{lambda log2(e) x'} with x' = x - xref; the prefactor e^{lambda xref}/N
+// is written through expm1 so that small |lambda| keeps full precision.
+__device__ __noinline__ bool exp_constants(const FactorPlan& F, const double* __restrict__ th,
+                                           double* kc, double* ec, double* lnorm2) {
+  const double a = F.lo[0], b = F.hi[0], xr = F.xref, L = b - a;
+  const double lam = th[F.par[0]];
+  kc[0] = lam * kLog2e;
+  if (lam == 0.0) {
+    *lnorm2 = -nl_log2(L);
+    ec[0] = a + 0.5 * L - xr;                           // E[x] - xref
+  } else {
+    const double z = lam * L;
+    *lnorm2 = (lam * (xr - a) - nl_log(nl_expm1(z) / lam)) * kLog2e;
+    ec[0] = a - xr + L * d_exp_h(z);
+  }
+  return true;
+}
+
+// Chebyshev series 1 + sum_j c_j T_j(u) on [a, b], u = (2x - a - b)/(b - a),
+// with norm N_C = (b - a) + sum_{j even} c_j (b - a)/(1 - j^2).
+__device__ __noinline__ bool cheb_constants(const FactorPlan& F, const double* __restrict__ th,
+                                            double* kc, double* ec) {
+  const double a = F.lo[0], b = F.hi[0], xr = F.xref;
+  const int k = F.order;
+  double N = b - a;
+  for (int jj = 1; jj <= k; ++jj) {
+    const double J = (jj % 2 == 0) ? (b - a) / (1.0 - double(jj * jj)) : 0.0;
+    N += th[F.par[jj - 1]] * J;
+    ec[jj] = J;
+  }
+  kc[0] = 2.0 / (b - a);
+  kc[1] = (2.0 * xr - a - b) / (b - a);
+  kc[2] = 1.0 / N;
+  for (int jj = 1; jj <= k; ++jj) kc[2 + jj] = th[F.par[jj - 1]] / N;
+  ec[0] = 1.0 / N;
+  return true;
+}
+
+// P-wave density (Eq. 4): coefficients 9/(32 pi) {1, FL, S3, .., S9}.
+__device__ __noinline__ void pwave_constants(const FactorPlan& F, const double* __restrict__ th,
+                                             double* kc, double* ec) {
+  const double kap = 9.0 / (32.0 * M_PI);
+  kc[0] = kap;
+  for (int k = 0; k < 8; ++k) kc[1 + k] = kap * th[F.par[k]];
+  ec[0] = kap;
+}
+
+// The prologue: every parameter-only term of the point theta (Sec. 2.4.1).
+__device__ __noinline__ void compute_constants(const Plan& P, const double* __restrict__ th,
+                                               ConstBlock* cb) {
+  bool ok = true;
+  for (int i = 0; i < P.npar; ++i) cb->theta[i] = th[i];
+  for (int ci = 0; ci < P.ncomp; ++ci) {
+    const CompPlan& C = P.comp[ci];
+    double lk2 = 0.0;
+    for (int k = 0; k < C.nfrac; ++k) {
+      const double f = th[C.frac_par[k]];
+      if (!(f >= 0.0 && f <= 1.0)) ok = false;
+      lk2 += nl_log2(C.frac_sign[k] > 0 ? f : 1.0 - f);
+    }
+    for (int j = 0; j < C.nfac; ++j) {
+      const FactorPlan& F = P.fac[C.fac[j]];
+      double* kc = cb->d + F.cst;
+      double* ec = cb->e + F.ecst;
+      double ln2 = 0.0;
+      switch (F.kind) {
+        case FK_GAUSS: ok = gauss_constants(F, th, kc, ec, &ln2) && ok; break;
+        case FK_EXP: ok = exp_constants(F, th, kc, ec, &ln2) && ok; break;
+        case FK_CHEB: ok = cheb_constants(F, th, kc, ec) && ok; break;
+        case FK_PWAVE: pwave_constants(F, th, kc, ec); break;
+        default: ok = false;
+      }
+      lk2 += ln2;
+    }
+    cb->d[C.cst_lk2] = lk2;
+  }
+  for (int i = 0; i < P.ncst; ++i) cb->f[i] = float(cb->d[i]);
+  for (int d = 0; d < P.ndim; ++d) {
+    cb->xd[d] = P.xref[d];
+    cb->xf[d] = float(P.xref[d]);
+  }
+  cb->domain_ok = ok ? 1 : 0;
+  cb->valid = 1;
+}
+
+// NLL and gradient from the K moment sums (chain rule through the mixture).
+// g: UML_MAX_PARAMS doubles of scratch (LDS).
+__device__ __noinline__ void epilogue(const Plan& P, const ConstBlock* cb,
+                                      const double* __restrict__ tot, double* __restrict__ out,
+                                      double* __restrict__ g) {
+  for (int i = 0; i < P.npar; ++i) g[i] = 0.0;
+  const double* th = cb->theta;
+  const double nll = -0.69314718055994530942 * tot[0];
+  for (int ci = 0; ci < P.ncomp; ++ci) {
+    const CompPlan& C = P.comp[ci];
+    const double R = tot[C.slot_r];
+    for (int k = 0; k < C.nfrac; ++k) {
+      const int p = C.frac_par[k];
+      g[p] -= C.frac_sign[k] > 0 ? R / th[p] : -R / (1.0 - th[p]);
+    }
+    for (int j = 0; j < C.nfac; ++j) {
+      const FactorPlan& F = P.fac[C.fac[j]];
+      const double* ec = cb->e + F.ecst;
+      const double* M = tot + F.mom;
+      switch (F.kind) {
+        case FK_GAUSS:
+          g[F.par[0]] -= M[0] * ec[0] - R * ec[1];
+          g[F.par[1]] -= M[1] * ec[2] - R * ec[3];
+          break;
+        case FK_EXP:
+          g[F.par[0]] -= M[0] - R * ec[0];
+          break;
+        case FK_CHEB:
+          for (int jj = 0; jj < F.order; ++jj) g[F.par[jj]] -= (M[jj] - R * ec[1 + jj]) * ec[0];
+          break;
+        case FK_PWAVE:
+          for (int k = 0; k < 8; ++k) g[F.par[k]] -= ec[0] * M[k];
+          break;
+      }
+    }
+  }
+  const bool bad = !cb->domain_ok || !isfinite(nll);
+  out[0] = bad ? INFINITY : nll;
+  for (int i = 0; i < P.nfree; ++i) out[1 + i] = bad ? 0.0 : g[P.free_idx[i]];
+}
+
+// Pass 2 over the tile partials of one job (whole workgroup), then the
+// epilogue.  tot: K + UML_MAX_PARAMS doubles of LDS; cb: the workgroup's
+// constants (LDS); hit: they came from the job's cache.
+__device__ __noinline__ void finalize(const Job& J, int K, double* tot, const ConstBlock* cb,
+                                      int hit, double* out_override) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nt = J.n_tiles;
+  for (int k = wv; k < K; k += kBlock / 64) {
+    const double* __restrict__ colp = J.partials + int64_t(k) * nt;
+    double s = 0.0, comp = 0.0;
+    for (int t = lane; t < nt; t += 64) {  // Neumaier, tile order
+      const double x = colp[t];
+      const double u = s + x;
+      comp += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
+      s = u;
+    }
+    double v = s + comp;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) tot[k] = v;
+  }
+  if (!hit) {  // keep this point's constants for the next evaluation
+    const int nw = int(sizeof(ConstBlock) / sizeof(int));
+    const int* src = reinterpret_cast<const int*>(cb);
+    int* dst = reinterpret_cast<int*>(J.cst);
+    for (int i = tid; i < nw; i += kBlock) dst[i] = src[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    epilogue(*J.plan, cb, tot, out_override ? out_override : J.out, tot + K);
+    atomicExch(J.counter, 0u);
+  }
+}
+
+// Copies of wave-invariant values in scalar registers.
+__device__ __forceinline__ float to_sgpr(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double to_sgpr(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(b & 0xffffffffu));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(b >> 32));
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Stages the parameter-only constants of theta into s_cb (LDS).  The job keeps
+// the block of the last point it evaluated; when theta matches it bit for bit
+// the block is copied, otherwise the first lane computes it (the prologue:
+// normalisations, combined prefactors, angular coefficients, all in FP64).
+__device__ __forceinline__ void stage_constants(const Job& J, const double* __restrict__ th,
+                                                ConstBlock* s_cb, int* s_hit) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int npar = J.plan->npar;
+    const ConstBlock* g = J.cst;
+    bool eq = true;
+    if (tid < npar) eq = __double_as_longlong(th[tid]) == __double_as_longlong(g->theta[tid]);
+    const bool hit = __all(eq) && g->valid;
+    if (hit) {
+      const int nw = int(sizeof(ConstBlock) / sizeof(int));
+      const int* src = reinterpret_cast<const int*>(g);
+      int* dst = reinterpret_cast<int*>(s_cb);
+      for (int i = tid; i < nw; i += 64) dst[i] = src[i];
+    } else if (tid == 0) {
+      compute_constants(*J.plan, th, s_cb);
+    }
+    if (tid == 0) *s_hit = hit ? 1 : 0;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------
+
+template <int K>
+__host__ __device__ constexpr int reduce_parts() {
+  int p = 1;
+  while (p * 2 * K <= kBlock && p * 2 <= 32) p *= 2;
+  return p;
+}
+
+template <class S, class P>
+__global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jobs,
+                                                      const int2* __restrict__ tmap,
+                                                      const double* __restrict__ theta_override,
+                                                      double* __restrict__ out_override) {
+  using T = typename P::T;
+  constexpr int K = S::K;
+  int jid = 0, tile = blockIdx.x;
+  if (tmap) {
+    const int2 t = tmap[blockIdx.x];
+    jid = t.x;
+    tile = t.y;
+    if (jid < 0) return;
+  }
+  const Job& J = jobs[jid];
+  __shared__ ConstBlock s_cb;
+  __shared__ int s_hit;
+  const double* __restrict__ th = (theta_override && !tmap) ? theta_override : J.theta;
+  stage_constants(J, th, &s_cb, &s_hit);
+  T c[S::ncst];
+#pragma unroll
+  for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
+  T xref[S::ndim];
+#pragma unroll
+  for (int d = 0; d < S::ndim; ++d) xref[d] = to_sgpr(P::xrefs(&s_cb)[d]);
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+
+  const int64_t tsize = int64_t(J.events_per_thread) * kBlock;
+  const int64_t base = int64_t(tile) * tsize;
+  const bool full = base + tsize <= J.n;
+  if (J.w) {
+    if (full)
+      process_tile<S, P, true, true>(J, base, c, xref, acc);
+    else
+      process_tile<S, P, true, false>(J, base, c, xref, acc);
+  } else {
+    if (full)
+      process_tile<S, P, false, true>(J, base, c, xref, acc);
+    else
+      process_tile<S, P, false, false>(J, base, c, xref, acc);
+  }
+
+  // pass 1: lanes -> tile partial, through LDS in a fixed order
+  constexpr int STRIDE = kBlock + 8;
+  constexpr int PARTS = reduce_parts<K>();
+  constexpr int CH = kBlock / PARTS;
+  // T-sized transpose buffer, reused by pass 2 for K + UML_MAX_PARAMS doubles
+  constexpr int LDS_T = (K * STRIDE * sizeof(T) > (K + UML_MAX_PARAMS) * sizeof(double))
+                            ? K * STRIDE
+                            : int((K + UML_MAX_PARAMS) * sizeof(double) / sizeof(T)) + 1;
+  __shared__ T red[LDS_T];
+  __shared__ double red2[K * PARTS];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k * STRIDE + tid] = acc[k];
+  __syncthreads();
+  if (tid < K * PARTS) {
+    const int k = tid / PARTS, p = tid % PARTS;
+    double s = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < CH; ++i) s += double(red[k * STRIDE + i * PARTS + p]);
+    red2[k * PARTS + p] = s;
+  }
+  __syncthreads();
+  if (tid < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p) s += red2[tid * PARTS + p];
+    J.partials[int64_t(tid) * J.n_tiles + tile] = s;
+    __threadfence();  // release the partial to the other workgroups
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = atomicAdd(J.counter, 1u);
+    s_last = (prev + 1u == unsigned(J.n_tiles)) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();  // acquire every tile's partial
+  finalize(J, K, reinterpret_cast<double*>(red), &s_cb, s_hit, out_override);
+}
+
+template <class S>
+void launch_eval(const LaunchArgs& a) {
+  if (a.precision == UML_MIXED)
+    hipLaunchKernelGGL((eval_kernel<S, PrecMixed>), dim3(a.grid), dim3(kBlock), 0, a.stream,
+                       a.jobs, a.tmap, a.theta, a.out);
+  else
+    hipLaunchKernelGGL((eval_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream, a.jobs,
+                       a.tmap, a.theta, a.out);
+}
+
+template <class S>
+Family make_family() {
+  return Family{S::sig(), S::K, S::ncst, &launch_eval<S>, nullptr};
+}
+
+// The compiled catalogue of model shapes.  Components are ordered by their
+// factor kinds, factors by (kind, dimension); dimensions are numbered
+// Gaussian/exponential first, then the P-wave's own order, then the rest.
+static const Family* families() {
+  static const Family table[] = {
+      make_family<Shape<Comp<Gauss<0>>>>(),                                  // Gauss
+      make_family<Shape<Comp<Exp<0>>>>(),                                    // exponential
+      make_family<Shape<Comp<Cheb<0, 1>>>>(),                                // Chebyshev
+      make_family<Shape<Comp<Cheb<0, 2>>>>(),
+      make_family<Shape<Comp<Cheb<0, 3>>>>(),
+      make_family<Shape<Comp<Cheb<0, 4>>>>(),
+      make_family<Shape<Comp<PWave<0, 1, 2>>>>(),                            // angular fit
+      make_family<Shape<Comp<Exp<0>>, Comp<Gauss<0>>>>(),                    // mass fit
+      make_family<Shape<Comp<Gauss<0>, PWave<1, 2, 3>>>>(),                  // 4-D signal
+      make_family<Shape<Comp<Exp<0>, Cheb<1, 2>, Cheb<2, 2>, Cheb<3, 2>>,  // 4-D model
+                        Comp<Gauss<0>, PWave<1, 2, 3>>>>(),
+      Family{"", 0, 0, nullptr, nullptr},
+  };
+  return table;
+}
+
+const Family* find_family(const std::string& sig) {
+  for (const Family* f = families(); f->eval; ++f)
+    if (f->sig == sig) return f;
+  return nullptr;
+}
+
+std::string family_list() {
+  std::string s;
+  for (const Family* f = families(); f->eval; ++f) s += (s.empty() ? "" : ", ") + f->sig;
+  return s;
+}
+
+}  // namespace uml

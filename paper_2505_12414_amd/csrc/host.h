@@ -1,0 +1,53 @@
+// Host-runtime internals of libuml (opaque handle layouts, helpers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "kernels.h"
+#include "uml_internal.h"
+
+struct uml_model {
+  uml::Plan plan;
+  uml::Plan* d_plan = nullptr;     // device copy
+  const uml::Family* family = nullptr;
+  int device = 0;
+};
+
+struct uml_data {
+  const uml_model* model = nullptr;
+  int64_t n = 0;
+  int weighted = 0;
+  int E = 0;                        // events per thread per tile
+  int n_tiles = 0;
+  void* d_events = nullptr;         // columns (+ weights), one allocation
+  void* d_work = nullptr;           // job, constants, partials, counter, outputs
+  uml::Job job{};                   // host copy of the device job
+  uml::Job* d_job = nullptr;
+  double* d_theta = nullptr;        // staging for host theta
+  double* d_out = nullptr;          // [1 + nfree]
+  double* d_hess_part = nullptr;    // Hessian tile partials (allocated on first use)
+  int64_t hess_part_elems = 0;
+  double* h_stage = nullptr;        // pinned host staging
+  int64_t bytes_events = 0;
+  int64_t bytes_work = 0;
+};
+
+namespace uml {
+
+int build_plan(const uml_model_desc* d, Plan& P, std::string& err);
+std::string plan_signature(const Plan& P);
+std::string plan_describe(const Plan& P);
+
+// thread-local error message
+int set_error(int code, const std::string& msg);
+
+#define UML_HIP_CHECK(expr)                                                         \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return ::uml::set_error(UML_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace uml

@@ -1,0 +1,36 @@
+// Host-side entry points of the device code (kernel launchers and the table
+// of compiled model shapes).
+#pragma once
+
+#include <string>
+
+#include "uml_internal.h"
+
+namespace uml {
+
+struct LaunchArgs {
+  const Job* jobs;       // device array of jobs
+  const int2* tmap;      // workgroup -> (job, tile), or nullptr: job 0, tile = workgroup
+  int grid;              // workgroups
+  double* out;           // overrides jobs[0].out when not nullptr
+  const double* theta;   // overrides jobs[0].theta when not nullptr
+  int precision;
+  hipStream_t stream;
+};
+
+// One compiled model shape: its signature (see plan_signature) and launchers.
+struct Family {
+  std::string sig;
+  int K;       // accumulators per event
+  int ncst;    // kernel constants
+  void (*eval)(const LaunchArgs&);
+  void (*hess)(const LaunchArgs&, double* hpart, int nfree);
+};
+
+// Returns the compiled family for a signature, or nullptr.
+const Family* find_family(const std::string& sig);
+// All compiled signatures, for error messages.
+std::string family_list();
+
+
+}  // namespace uml

@@ -1,0 +1,159 @@
+// Internal layout shared by the host runtime and the kernels of libuml.
+//
+// A model tree is expanded into a mixture of products
+//     P(x) = sum_c F_c prod_{f in c} p_f(x_{dims(f)}),
+// with F_c the product of the SUM fractions (f or 1 - f) on the path to
+// component c.  Each factor is a catalogue leaf (Gaussian, exponential,
+// Chebyshev series, P-wave density).  The event kernels work in base-2 log
+// space per component:
+//     S_c = 2^{E_c} V_c,   E_c = log2 K_c + sum_{exp-type f} e_f(x),
+//     V_c = prod_{polynomial-type f} v_f(x),
+// where K_c collects every parameter-only factor (fractions, the Gaussian and
+// exponential normalisations).  Those parameter-only terms are computed once
+// per parameter point by the prologue (the paper's hoisting of
+// parameter-dependent terms, Sec. 2.4.1 and Eq. 3).
+//
+// Per event the kernels accumulate, weighted by w:
+//     slot 0:            log2 P
+//     per component c:   r_c = S_c / P                     (responsibility)
+//     Gaussian f in c:   r_c d, r_c d^2 with d = x - mu
+//     exponential f:     r_c x'   (x' = x - xref, a per-dimension shift)
+//     Chebyshev f:       q_{c,f} T_j(u), j = 1..k
+//     P-wave f:          q_{c,f} b_k, the 8 angular terms
+// where q_{c,f} = r_c / v_f.  The epilogue turns these sums into the NLL and
+// its gradient in FP64 (chain rule through the mixture).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "uml.h"
+
+namespace uml {
+
+constexpr int kBlock = 256;           // threads per workgroup
+constexpr int kMaxComp = 4;           // mixture components
+constexpr int kMaxFacPerComp = 4;     // factors per component
+constexpr int kMaxFac = 16;           // factors in the whole mixture
+constexpr int kMaxK = 64;             // accumulators per event
+constexpr int kMaxCst = 128;          // kernel constants
+constexpr int kMaxECst = 128;         // epilogue constants
+constexpr int kMaxCheb = 4;
+
+enum FactorKind { FK_GAUSS = 1, FK_EXP = 2, FK_CHEB = 3, FK_PWAVE = 4 };
+
+// Kernel constants, moments and epilogue constants per factor kind; the
+// compile-time shapes and the host plan builder both use these.
+__host__ __device__ constexpr int fk_ncst(int kind, int order) {
+  return kind == FK_GAUSS ? 2 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order + 3 : 9;
+}
+__host__ __device__ constexpr int fk_nmom(int kind, int order) {
+  return kind == FK_GAUSS ? 2 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order : 8;
+}
+__host__ __device__ constexpr int fk_necst(int kind, int order) {
+  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order + 1 : 1;
+}
+__host__ __device__ constexpr bool fk_expo(int kind) {
+  return kind == FK_GAUSS || kind == FK_EXP;
+}
+
+struct FactorPlan {
+  int kind, order;   // order: Chebyshev order (0 otherwise)
+  int dim[3];        // kernel dimensions (canonical order)
+  int par[8];        // parameter indices
+  int cst;           // offset of its kernel constants
+  int ecst;          // offset of its epilogue constants
+  int mom;           // first moment slot
+  double lo[3], hi[3];
+  double xref;       // shift of dim[0] (0 if the dimension is not shifted)
+};
+
+struct CompPlan {
+  int nfac;
+  int fac[kMaxFacPerComp];  // factor indices, in kernel order
+  int nfrac;
+  int frac_par[8];          // SUM fraction parameters on the path
+  int frac_sign[8];         // +1: f, -1: 1 - f
+  int cst_lk2;              // offset of log2 K_c
+  int slot_r;               // moment slot of r_c
+};
+
+struct Plan {
+  int ncomp;
+  CompPlan comp[kMaxComp];
+  int nfac;
+  FactorPlan fac[kMaxFac];
+  int K;       // accumulators (slot 0 = log2 P)
+  int ncst;    // kernel constants
+  int necst;   // epilogue constants
+  int ndim;    // kernel dimensions
+  int npar, nfree;
+  int free_idx[UML_MAX_PARAMS];  // free position -> parameter
+  int free_pos[UML_MAX_PARAMS];  // parameter -> free position or -1
+  int dim_of_user[UML_MAX_DIMS]; // user dimension -> kernel dimension
+  int user_of_dim[UML_MAX_DIMS]; // kernel dimension -> user dimension
+  double lo[UML_MAX_DIMS], hi[UML_MAX_DIMS];  // per kernel dimension
+  double xref[UML_MAX_DIMS];     // per kernel dimension (0: not shifted)
+  int precision;
+};
+
+// Parameter-dependent constants for one evaluation (written by the prologue).
+struct ConstBlock {
+  double d[kMaxCst];    // kernel constants, FP64
+  float f[kMaxCst];     // the same, rounded to FP32 (mixed arithmetic)
+  double e[kMaxECst];   // epilogue constants
+  double theta[UML_MAX_PARAMS];
+  double xd[UML_MAX_DIMS];  // per-dimension shifts (FP64)
+  float xf[UML_MAX_DIMS];   // the same in FP32 (exact: FP32 values)
+  int domain_ok;        // 0 if theta is outside the model's domain
+  int valid;            // 1 once written: theta[] is the key of this block
+};
+
+// Device-resident state of one BFGS fit (one per job in fit mode).
+struct FitState {
+  double x[UML_MAX_PARAMS];       // accepted point (free parameters)
+  double g[UML_MAX_PARAMS];       // gradient there
+  double f;                       // NLL there
+  double V[UML_MAX_PARAMS * UML_MAX_PARAMS];  // inverse-Hessian estimate
+  double p[UML_MAX_PARAMS];       // search direction
+  double gp;                      // g . p
+  double alpha;                   // current trial step
+  double edm;
+  double theta[UML_MAX_PARAMS];   // full parameter vector of the trial point
+  int phase;                      // 0: first evaluation, 1: line search
+  int n_iter, n_eval, n_ls;
+  int done;                       // 0 running, 1 finished
+  int status;                     // UML_FIT_*
+  double edm_tol;
+  int max_iter;
+};
+
+// One dataset's share of a launch.
+struct Job {
+  const void* col[UML_MAX_DIMS];  // event columns, kernel-dimension order
+  const void* w;                  // weights or nullptr
+  int64_t n;                      // events
+  int32_t n_tiles;
+  int32_t events_per_thread;      // E: events per thread per tile
+  ConstBlock* cst;                // constants of the last evaluated point (cache)
+  double* partials;               // [K][n_tiles]
+  unsigned int* counter;          // last-workgroup counter
+  double* out;                    // [1 + nfree]: nll, gradient
+  const Plan* plan;               // device copy of the plan
+  FitState* fit;                  // BFGS state (fit mode) or nullptr
+  const double* theta;            // parameter vector to evaluate (device)
+};
+
+// Events per thread per tile for a dataset of n events: enough tiles to
+// fill the chip at 1e6 events, few enough partial sums at 1e7 and beyond.
+// A pure function of n and the precision, so a dataset is reduced in the same
+// order whatever else shares the launch.
+inline int events_per_thread(int64_t n, int precision) {
+  const int vw = precision == UML_MIXED ? 4 : 2;
+  int64_t per = n / (int64_t(kBlock) * 1024);
+  int e = vw;
+  while (e < per && e < 32) e *= 2;
+  return e;
+}
+
+}  // namespace uml

@@ -1,0 +1,372 @@
+"""Python binding of libuml (ctypes; argument marshalling only).
+
+Every function here calls the C ABI declared in include/uml.h under the same
+name; all arithmetic runs in the library's HIP kernels.  The library must
+have been built (``python -m paper_2505_12414_amd.build``); loading fails
+loudly otherwise -- there is no CPU fallback.
+
+Model descriptions are plain dicts::
+
+    {"dims":   [{"name": "m", "lo": 5.0, "hi": 5.6}, ...],
+     "params": [{"name": "mu", "value": 5.28, "fixed": False}, ...],
+     "nodes":  [{"kind": "gauss", "dims": [0], "params": [0, 1]}, ...,
+                {"kind": "sum", "children": [0, 1], "params": [3]}],
+     "root": 2}
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libuml.so")
+
+UML_OK = 0
+UML_E_INVALID = -1
+UML_E_UNSUPPORTED = -2
+UML_E_EVENT_DOMAIN = -3
+UML_E_PDF_NONPOSITIVE = -4
+UML_E_HIP = -5
+UML_E_NOMEM = -6
+UML_E_NOT_PD = -7
+UML_E_BUDGET = -8
+UML_E_QUEUE_FULL = -9
+UML_E_TIMEOUT = -10
+
+UML_FP64, UML_MIXED = 0, 1
+UML_F32, UML_F64 = 0, 1
+UML_DATA_DEVICE_SRC = 1
+MAX_PARAMS = 32
+
+KINDS = {"gauss": 1, "exp": 2, "cheb": 3, "pwave": 4, "prod": 5, "sum": 6}
+FIT_STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "hessian_not_pd",
+              4: "pdf_nonpositive", 5: "cancelled"}
+
+
+class UmlError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class uml_dim(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double)]
+
+
+class uml_param(C.Structure):
+    _fields_ = [("value", C.c_double), ("lo", C.c_double), ("hi", C.c_double),
+                ("fixed", C.c_int32)]
+
+
+class uml_node(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dims", C.c_int32 * 3), ("n_params", C.c_int32),
+                ("params", C.c_int32 * 8), ("n_children", C.c_int32),
+                ("children", C.c_int32 * 4)]
+
+
+class uml_model_desc(C.Structure):
+    _fields_ = [("n_dims", C.c_int32), ("dims", C.POINTER(uml_dim)),
+                ("n_params", C.c_int32), ("params", C.POINTER(uml_param)),
+                ("n_nodes", C.c_int32), ("nodes", C.POINTER(uml_node)),
+                ("root", C.c_int32), ("precision", C.c_int32)]
+
+
+class uml_fit_options(C.Structure):
+    _fields_ = [("edm_tol", C.c_double), ("max_iter", C.c_int32), ("polish", C.c_int32),
+                ("want_cov", C.c_int32)]
+
+
+class uml_fit_result(C.Structure):
+    _fields_ = [("params", C.c_double * MAX_PARAMS), ("errors", C.c_double * MAX_PARAMS),
+                ("cov", C.c_double * (MAX_PARAMS * MAX_PARAMS)), ("nll", C.c_double),
+                ("edm", C.c_double), ("n_free", C.c_int32), ("n_iter", C.c_int32),
+                ("n_eval", C.c_int32), ("status", C.c_int32), ("ticket", C.c_uint64),
+                ("latency_s", C.c_double)]
+
+
+class uml_server_options(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("hbm_budget", C.c_int64),
+                ("max_pending", C.c_int32), ("fit", uml_fit_options)]
+
+
+class uml_request(C.Structure):
+    _fields_ = [("n_events", C.c_int64), ("cols", C.POINTER(C.c_void_p)), ("dtype", C.c_int32),
+                ("w", C.c_void_p), ("start", C.POINTER(C.c_double))]
+
+
+class uml_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("finished", C.c_int64),
+                ("pending", C.c_int64), ("active", C.c_int64), ("iterations", C.c_int64),
+                ("resident_bytes", C.c_int64)]
+
+
+# name -> (restype, argtypes)
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+SIGNATURES = {
+    "uml_model_create": (C.c_int, [C.POINTER(uml_model_desc), C.POINTER(_P)]),
+    "uml_model_destroy": (None, [_P]),
+    "uml_model_n_free": (C.c_int, [_P]),
+    "uml_model_describe": (C.c_int, [_P, C.c_char_p, C.c_int32]),
+    "uml_data_create": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_void_p), C.c_int32, _P,
+                                  C.c_int32, _P, C.POINTER(_P)]),
+    "uml_data_destroy": (None, [_P]),
+    "uml_data_n_events": (C.c_int64, [_P]),
+    "uml_eval_nll": (C.c_int, [_P, _P, _DP, _DP, _P]),
+    "uml_eval_nll_grad": (C.c_int, [_P, _P, _DP, _DP, _DP, _P]),
+    "uml_eval_nll_grad_dev": (C.c_int, [_P, _P, _P, _P, _P]),
+    "uml_eval_hessian": (C.c_int, [_P, _P, _DP, _DP, _DP, _DP, _DP, _P]),
+    "uml_fit_options_default": (None, [C.POINTER(uml_fit_options)]),
+    "uml_fit": (C.c_int, [_P, _P, _DP, C.POINTER(uml_fit_options), C.POINTER(uml_fit_result)]),
+    "uml_fit_batch": (C.c_int, [_P, C.POINTER(_P), C.c_int32, _DP, C.POINTER(uml_fit_options),
+                                C.POINTER(uml_fit_result)]),
+    "uml_server_options_default": (None, [C.POINTER(uml_server_options)]),
+    "uml_server_create": (C.c_int, [_P, C.POINTER(uml_server_options), C.POINTER(_P)]),
+    "uml_server_submit": (C.c_int, [_P, C.POINTER(uml_request), C.POINTER(C.c_uint64)]),
+    "uml_server_poll": (C.c_int, [_P, C.POINTER(uml_fit_result), C.c_int32,
+                                  C.POINTER(C.c_int32), C.c_int32]),
+    "uml_server_stats_get": (C.c_int, [_P, C.POINTER(uml_server_stats)]),
+    "uml_server_drain": (C.c_int, [_P]),
+    "uml_server_destroy": (None, [_P]),
+    "uml_last_error": (C.c_char_p, []),
+    "uml_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libuml.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2505_12414_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().uml_last_error().decode()
+
+
+def check(rc, allow=()):
+    if rc != UML_OK and rc not in allow:
+        raise UmlError(rc, last_error())
+    return rc
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_DP)
+
+
+class Model:
+    """uml_model_create / uml_model_destroy."""
+
+    def __init__(self, desc, precision="mixed"):
+        self.desc = desc
+        prec = {"mixed": UML_MIXED, "fp64": UML_FP64}[precision]
+        self.precision = precision
+        dims = (uml_dim * len(desc["dims"]))(*[uml_dim(d["lo"], d["hi"]) for d in desc["dims"]])
+        ps = desc["params"]
+        params = (uml_param * max(1, len(ps)))(*[
+            uml_param(p["value"], p.get("lo", -1e30), p.get("hi", 1e30), int(p.get("fixed", False)))
+            for p in ps])
+        nodes = (uml_node * len(desc["nodes"]))()
+        for i, nd in enumerate(desc["nodes"]):
+            n = nodes[i]
+            n.kind = KINDS[nd["kind"]]
+            for k, d in enumerate(nd.get("dims", [])):
+                n.dims[k] = d
+            pp = nd.get("params", [])
+            n.n_params = len(pp)
+            for k, p in enumerate(pp):
+                n.params[k] = p
+            ch = nd.get("children", [])
+            n.n_children = len(ch)
+            for k, c in enumerate(ch):
+                n.children[k] = c
+        d = uml_model_desc(len(desc["dims"]), dims, len(ps), params, len(desc["nodes"]), nodes,
+                           int(desc["root"]), prec)
+        h = _P()
+        check(lib().uml_model_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.n_params = len(ps)
+        self.n_dims = len(desc["dims"])
+        self.n_free = lib().uml_model_n_free(h)
+        self.free = np.array([not p.get("fixed", False) for p in ps])
+        self.theta0 = np.array([p["value"] for p in ps], dtype=np.float64)
+
+    def describe(self):
+        buf = C.create_string_buffer(4096)
+        check(lib().uml_model_describe(self.handle, buf, 4096))
+        return buf.value.decode()
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.uml_model_destroy(self.handle)
+            self.handle = None
+
+
+class Data:
+    """uml_data_create / uml_data_destroy.  events: array (n_dims, n) of
+    float32 or float64 (host numpy, or a torch CUDA tensor for device upload)."""
+
+    def __init__(self, model, events, weights=None, stream=None):
+        self.model = model
+        flags = 0
+        keep = []
+        if hasattr(events, "is_cuda") and events.is_cuda:
+            import torch
+            ev = events.contiguous()
+            if ev.dim() == 1:
+                ev = ev.reshape(1, -1)
+            dtype = UML_F32 if ev.dtype == torch.float32 else UML_F64
+            if ev.dtype not in (torch.float32, torch.float64):
+                raise TypeError("events must be float32 or float64")
+            n = ev.shape[1]
+            cols = (C.c_void_p * ev.shape[0])(*[ev[d].data_ptr() for d in range(ev.shape[0])])
+            wptr = None
+            if weights is not None:
+                wt = weights.to(ev.dtype).contiguous()
+                keep.append(wt)
+                wptr = wt.data_ptr()
+            flags |= UML_DATA_DEVICE_SRC
+            keep.append(ev)
+        else:
+            ev = np.asarray(events)
+            if ev.ndim == 1:
+                ev = ev.reshape(1, -1)
+            if ev.dtype not in (np.float32, np.float64):
+                ev = ev.astype(np.float64)
+            ev = np.ascontiguousarray(ev)
+            dtype = UML_F32 if ev.dtype == np.float32 else UML_F64
+            n = ev.shape[1]
+            cols = (C.c_void_p * ev.shape[0])(*[ev[d].ctypes.data for d in range(ev.shape[0])])
+            wptr = None
+            if weights is not None:
+                wt = np.ascontiguousarray(np.asarray(weights, dtype=ev.dtype))
+                if wt.shape != (n,):
+                    raise ValueError("weights must have one entry per event")
+                keep.append(wt)
+                wptr = wt.ctypes.data
+            keep.append(ev)
+        if ev.shape[0] != model.n_dims:
+            raise ValueError(f"events must have {model.n_dims} rows")
+        h = _P()
+        check(lib().uml_data_create(model.handle, n, cols, dtype, wptr, flags, _stream_ptr(stream),
+                                    C.byref(h)))
+        self.handle = h
+        self.n = n
+        self.weighted = weights is not None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.uml_data_destroy(self.handle)
+            self.handle = None
+
+
+def _theta(model, theta):
+    th = np.ascontiguousarray(model.theta0 if theta is None else theta, dtype=np.float64)
+    if th.shape != (model.n_params,):
+        raise ValueError(f"theta must hold all {model.n_params} parameters")
+    return th
+
+
+def uml_eval_nll(model, data, theta=None, stream=None, allow_nonpositive=True):
+    th = _theta(model, theta)
+    out = C.c_double()
+    check(lib().uml_eval_nll(model.handle, data.handle, _dptr(th), C.byref(out),
+                             _stream_ptr(stream)),
+          allow=(UML_E_PDF_NONPOSITIVE,) if allow_nonpositive else ())
+    return out.value
+
+
+def uml_eval_nll_grad(model, data, theta=None, stream=None, allow_nonpositive=True):
+    """Returns (nll, gradient over the free parameters)."""
+    th = _theta(model, theta)
+    out = C.c_double()
+    g = np.zeros(max(1, model.n_free))
+    check(lib().uml_eval_nll_grad(model.handle, data.handle, _dptr(th), C.byref(out), _dptr(g),
+                                  _stream_ptr(stream)),
+          allow=(UML_E_PDF_NONPOSITIVE,) if allow_nonpositive else ())
+    return out.value, g[:model.n_free].copy()
+
+
+def uml_eval_nll_grad_dev(model, data, d_theta, d_out, stream=None):
+    """Stream-ordered: d_theta (float64 CUDA tensor, n_params) -> d_out
+    (float64 CUDA tensor, 1 + n_free).  stream: torch.cuda.Stream, raw
+    hipStream_t int, or None for torch's current stream."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    check(lib().uml_eval_nll_grad_dev(model.handle, data.handle, d_theta.data_ptr(),
+                                      d_out.data_ptr(), _stream_ptr(stream)))
+
+
+def uml_eval_hessian(model, data, theta=None, want_w2=False, stream=None, allow_nonpositive=True):
+    """Returns (nll, grad, hess[, w2]) over the free parameters."""
+    th = _theta(model, theta)
+    nf = model.n_free
+    out = C.c_double()
+    g = np.zeros(max(1, nf))
+    h = np.zeros(max(1, nf * nf))
+    w2 = np.zeros(max(1, nf * nf)) if want_w2 else None
+    check(lib().uml_eval_hessian(model.handle, data.handle, _dptr(th), C.byref(out), _dptr(g),
+                                 _dptr(h), _dptr(w2) if want_w2 else None, _stream_ptr(stream)),
+          allow=(UML_E_PDF_NONPOSITIVE,) if allow_nonpositive else ())
+    res = (out.value, g[:nf].copy(), h[:nf * nf].reshape(nf, nf).copy())
+    return res + ((w2[:nf * nf].reshape(nf, nf).copy(),) if want_w2 else ())
+
+
+def fit_options(edm_tol=1e-6, max_iter=1000, polish=0, want_cov=1):
+    o = uml_fit_options()
+    lib().uml_fit_options_default(C.byref(o))
+    o.edm_tol, o.max_iter, o.polish, o.want_cov = edm_tol, max_iter, polish, want_cov
+    return o
+
+
+def result_dict(model, r):
+    nf = r.n_free
+    return {"theta": np.array(r.params[:model.n_params]),
+            "errors": np.array(r.errors[:model.n_params]),
+            "cov": np.array(r.cov[:nf * nf]).reshape(nf, nf), "nll": r.nll, "edm": r.edm,
+            "n_iter": r.n_iter, "n_eval": r.n_eval, "status": r.status,
+            "status_name": FIT_STATUS.get(r.status, str(r.status)), "ticket": r.ticket,
+            "latency_s": r.latency_s}
+
+
+def uml_fit(model, data, start=None, **opts):
+    th = _theta(model, start)
+    o = fit_options(**opts)
+    r = uml_fit_result()
+    check(lib().uml_fit(model.handle, data.handle, _dptr(th), C.byref(o), C.byref(r)))
+    return result_dict(model, r)
+
+
+def uml_fit_batch(model, datas, starts=None, **opts):
+    n = len(datas)
+    st = np.ascontiguousarray(np.tile(model.theta0, (n, 1)) if starts is None else starts,
+                              dtype=np.float64)
+    hs = (_P * n)(*[d.handle for d in datas])
+    o = fit_options(**opts)
+    rs = (uml_fit_result * n)()
+    check(lib().uml_fit_batch(model.handle, hs, n, _dptr(st), C.byref(o), rs))
+    return [result_dict(model, r) for r in rs]
+
+
+def uml_version():
+    return lib().uml_version().decode()

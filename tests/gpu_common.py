@@ -1,0 +1,126 @@
+"""Shared helpers of the GPU parity tests: the same seeded events and
+parameter points go to the HIP path (through the C ABI) and to the oracle."""
+import math
+
+import numpy as np
+
+import oracle
+from paper_2505_12414_amd import datagen as G
+from paper_2505_12414_amd import uml
+from paper_2505_12414_amd import workloads as W
+
+# Tolerances.  FP64 mode: NLL to 1e-12 relative.  Mixed mode (FP32 per-event
+# arithmetic, FP64 sums): NLL to 1e-6 relative.  Gradient components are
+# compared in units of the NLL change per statistical standard deviation of
+# that parameter, |dg_k| * sigma_k: a gradient error e in those units moves a
+# fitted value by e standard deviations.
+TOL = {"fp64": {"nll": 1e-12, "grad_sigma": 1e-8},
+       "mixed": {"nll": 1e-6, "grad_sigma": 1e-4}}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gauss_desc(lo=5.0, hi=5.6, mu=5.28, sigma=0.02):
+    return {"dims": [{"name": "m", "lo": lo, "hi": hi}],
+            "params": [{"name": "mu", "value": mu}, {"name": "sigma", "value": sigma}],
+            "nodes": [{"kind": "gauss", "dims": [0], "params": [0, 1]}], "root": 0}
+
+
+def exp_desc(lo=5.0, hi=5.6, lam=-1.5):
+    return {"dims": [{"name": "m", "lo": lo, "hi": hi}],
+            "params": [{"name": "lambda", "value": lam}],
+            "nodes": [{"kind": "exp", "dims": [0], "params": [0]}], "root": 0}
+
+
+def cheb_desc(coeffs, lo=-1.0, hi=2.0):
+    return {"dims": [{"name": "x", "lo": lo, "hi": hi}],
+            "params": [{"name": f"c{j+1}", "value": c} for j, c in enumerate(coeffs)],
+            "nodes": [{"kind": "cheb", "dims": [0], "params": list(range(len(coeffs)))}],
+            "root": 0}
+
+
+def sig4d_desc():
+    d = W.angmass4d()
+    params = d["params"][:10]
+    return {"dims": d["dims"], "params": params,
+            "nodes": [d["nodes"][0], d["nodes"][1], {"kind": "prod", "children": [0, 1]}],
+            "root": 2}
+
+
+def rng_events(desc, n, seed, dtype):
+    """Seeded events for any description (the generators for the workload
+    models, uniform points inside the ranges otherwise)."""
+    names = [d["name"] for d in desc["dims"]]
+    if names == ["m", "ctl", "ctk", "phi"] and len(desc["params"]) == 18:
+        return G.gen_angmass4d(n, seed, dtype=dtype)
+    if names == ["m"] and len(desc["params"]) == 4:
+        return G.gen_mass1d(n, seed, dtype=dtype)
+    if names == ["ctl", "ctk", "phi"]:
+        return G.gen_pwave3d(n, seed, dtype=dtype)
+    rng = np.random.default_rng(seed)
+    cols = [G.to_storage(rng.uniform(d["lo"], d["hi"], n), d["lo"], d["hi"], dtype)
+            for d in desc["dims"]]
+    if names == ["m"] and desc["nodes"][0]["kind"] == "gauss":
+        p = desc["params"]
+        cols = [G.to_storage(G.trunc_normal(rng, n, p[0]["value"], p[1]["value"], 5.0, 5.6),
+                             5.0, 5.6, dtype)]
+    return np.stack(cols)
+
+
+def sigmas(om, x, theta, w=None, sample=20000):
+    """Statistical standard deviations sqrt(diag H^-1) from the oracle Hessian
+    (on a subsample for large inputs, scaled to the full size)."""
+    n = x.shape[1]
+    if n > sample:
+        idx = np.linspace(0, n - 1, sample).astype(np.int64)
+        xs, ws, scale = x[:, idx], (None if w is None else w[idx]), n / sample
+    else:
+        xs, ws, scale = x, w, 1.0
+    _, _, h, _ = om.nll(xs, theta, w=ws, order=2)
+    free = om.free
+    H = h[np.ix_(free, free)] * scale
+    return np.sqrt(np.abs(np.diag(np.linalg.inv(H))))
+
+
+def compare(desc, precision, x, theta, w=None, um=None, ud=None, om=None, sig=None, tag=""):
+    """Evaluates NLL + gradient on the GPU and in the oracle; returns the
+    relative NLL error and the per-parameter gradient error in sigma units."""
+    om = om or oracle.Model(desc)
+    um = um or uml.Model(desc, precision)
+    ud = ud or uml.Data(um, x, weights=w)
+    x64 = x.astype(np.float64)
+    w64 = None if w is None else np.asarray(w, dtype=np.float64)
+    say(f"case {tag} precision={precision} n={x.shape[1]} theta={np.round(theta, 5).tolist()}")
+    nll_g, g_g = uml.uml_eval_nll_grad(um, ud, theta)
+    nll_o, g_o, _, bad = om.nll(x64, theta, w=w64, order=1)
+    assert bad == 0
+    g_o = g_o[om.free]
+    if sig is None:
+        sig = sigmas(om, x64, theta, w64)
+    rel = abs(nll_g - nll_o) / abs(nll_o)
+    gerr = np.abs(g_g - g_o) * sig
+    return rel, gerr, (nll_g, nll_o, g_g, g_o)
+
+
+def random_points(theta0, sig, free, k, seed, width=3.0):
+    """Parameter points within +-width standard deviations of theta0."""
+    rng = np.random.default_rng(seed)
+    pts = []
+    for _ in range(k):
+        th = np.array(theta0, dtype=np.float64).copy()
+        th[free] += rng.uniform(-width, width, int(free.sum())) * sig
+        pts.append(th)
+    return pts
+
+
+def assert_parity(rel, gerr, precision, tag):
+    t = TOL[precision]
+    assert rel <= t["nll"], f"{tag}: NLL relative error {rel:.3e} > {t['nll']}"
+    assert np.all(gerr <= t["grad_sigma"]), \
+        f"{tag}: gradient error (sigma units) {gerr.max():.3e} > {t['grad_sigma']}: {gerr}"
+
+
+def isfinite(v):
+    return math.isfinite(v)
