@@ -38,6 +38,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--events", type=int, default=1_000_000)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--model", default="angmass4d", choices=["angmass4d", "mass1d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -51,14 +52,20 @@ def main():
     from paper_2505_12414_amd import workloads as W
 
     n = args.events
-    desc = W.angmass4d()
     dtype = np.float32 if args.precision == "mixed" else np.float64
-    x = G.gen_angmass4d(n, seed=20250512, dtype=dtype)
+    if args.model == "angmass4d":
+        desc = W.angmass4d()
+        x = G.gen_angmass4d(n, seed=20250512, dtype=dtype)
+        truth = W.angmass4d_truth_vector()
+    else:
+        desc = W.mass1d()
+        x = G.gen_mass1d(n, seed=20250512, dtype=dtype)
+        truth = [5.28, 0.02, -1.5, 0.3]
     torch.cuda.init()
     dev = torch.device("cuda:0")
     model = uml.Model(desc, args.precision)
     data = uml.Data(model, x)
-    theta = torch.tensor(W.angmass4d_truth_vector(), dtype=torch.float64, device=dev)
+    theta = torch.tensor(truth, dtype=torch.float64, device=dev)
     out = torch.empty(1 + model.n_free, dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream(device=dev)
 
@@ -83,15 +90,22 @@ def main():
     value = n * args.steps / (gpu_ms * 1e-3)
     nll = float(out[0].item())
 
-    flop = FLOP_PER_EVENT_4D * n
-    achieved_tflops = flop / (ms_per_step * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
-                "peak": PEAK_FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
-                "kernel": "eval_kernel<angmass4d, mixed>" if args.precision == "mixed"
-                else "eval_kernel<angmass4d, fp64>",
-                "flop_per_event": FLOP_PER_EVENT_4D,
-                "bytes_per_event": 16 if args.precision == "mixed" else 32}
+    esize = 4 if args.precision == "mixed" else 8
+    kname = f"eval_kernel<{args.model}, {args.precision}>"
+    if args.model == "angmass4d":
+        flop = FLOP_PER_EVENT_4D * n
+        achieved = flop / (ms_per_step * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3),
+                    "peak": PEAK_FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
+                    "kernel": kname, "flop_per_event": FLOP_PER_EVENT_4D,
+                    "bytes_per_event": 4 * esize}
+    else:
+        nbytes = esize * n
+        achieved = nbytes / (ms_per_step * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                    "kernel": kname, "bytes_per_event": esize}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -99,7 +113,7 @@ def main():
         om = oracle.Model(desc)
         k = min(n, 100_000)
         xs = x[:, :k].astype(np.float64)
-        th = np.array(W.angmass4d_truth_vector())
+        th = np.array(truth)
         reps, t = 0, 0.0
         t0 = time.perf_counter()
         while t < 10.0:
@@ -108,15 +122,19 @@ def main():
             t = time.perf_counter() - t0
         cpu = {"value": round(k * reps / t, 1), "unit": "events/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{k} events of the same 4-D dataset, NLL+gradient, {reps} evaluations, "
+               "sample": f"{k} events of the same dataset, NLL+gradient, {reps} evaluations, "
                          f"{t:.1f} s, single thread"}
 
-    rec = {"metric": "NLL+grad events/s at 1e6 events (4D)", "value": round(value, 1),
+    metric = ("NLL+grad events/s at 1e6 events (4D)" if args.model == "angmass4d"
+              else "NLL+grad events/s (1D mass model)")
+    wl = ("4-D angular x mass NLL+gradient" if args.model == "angmass4d"
+          else "1-D mass-model NLL+gradient")
+    rec = {"metric": metric, "value": round(value, 1),
            "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(ms_per_step, 6), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32" if args.precision == "mixed" else "f64",
            "data": "synthetic",
-           "config": {"workload": f"4-D angular x mass NLL+gradient, {n} events, "
+           "config": {"workload": f"{wl}, {n} events, "
                                   f"{'FP32 compute / FP64 accumulate' if args.precision == 'mixed' else 'FP64'}",
                       "events": n, "free_params": model.n_free, "precision": args.precision},
            "roofline": roofline, "cpu_baseline": cpu,

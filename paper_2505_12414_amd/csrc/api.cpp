@@ -167,8 +167,8 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
   const int64_t o_theta = align_up(o_cst + sizeof(ConstBlock), 256);
   const int64_t o_out = align_up(o_theta + sizeof(double) * UML_MAX_PARAMS, 256);
   const int64_t o_cnt = align_up(o_out + sizeof(double) * (1 + UML_MAX_PARAMS), 256);
-  const int64_t o_part = align_up(o_cnt + 256, 256);
-  d->bytes_work = o_part + int64_t(sizeof(double)) * P.K * d->n_tiles;
+  const int64_t o_part = align_up(o_cnt + sizeof(unsigned) * kCounterWords, 256);
+  d->bytes_work = o_part + int64_t(sizeof(double)) * P.K * (d->n_tiles + kGroups);
 
   auto fail = [&](hipError_t e, const char* what) {
     if (d->d_events) (void)hipFree(d->d_events);
@@ -204,6 +204,7 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
   J.plan = m->d_plan;
   J.fit = nullptr;
   J.theta = d->d_theta;
+  J.npar = P.npar;
   e = hipMemcpyAsync(d->d_events, host.data(), host.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(wbase, 0, o_part, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s);
@@ -239,6 +240,7 @@ static int check_pair(const uml_model* m, const uml_data* d, const char* fn) {
 static int queue_eval(const uml_model* m, const uml_data* d, const double* d_theta, double* d_out,
                       hipStream_t s) {
   LaunchArgs a{};
+  a.job0 = d->job;
   a.jobs = d->d_job;
   a.tmap = nullptr;
   a.grid = d->n_tiles;

@@ -611,38 +611,65 @@ __device__ __noinline__ void epilogue(const Plan& P, const ConstBlock* cb,
   for (int i = 0; i < P.nfree; ++i) out[1 + i] = bad ? 0.0 : g[P.free_idx[i]];
 }
 
-// Pass 2 over the tile partials of one job (whole workgroup), then the
-// epilogue.  tot: K + UML_MAX_PARAMS doubles of LDS; cb: the workgroup's
-// constants (LDS); hit: they came from the job's cache.
-__device__ __noinline__ void finalize(const Job& J, int K, double* tot, const ConstBlock* cb,
-                                      int hit, double* out_override) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nt = J.n_tiles;
-  for (int k = wv; k < K; k += kBlock / 64) {
-    const double* __restrict__ colp = J.partials + int64_t(k) * nt;
+// Bulk copy of n bytes (a multiple of 16, both 16-byte aligned) by the
+// whole workgroup: every load is issued before any is waited for.
+__device__ __forceinline__ void bulk_copy16(void* dst, const void* src, int nbytes) {
+  const int4* s4 = static_cast<const int4*>(src);
+  int4* d4 = static_cast<int4*>(dst);
+  const int n = nbytes / 16;
+  for (int i = threadIdx.x; i < n; i += kBlock) d4[i] = s4[i];
+}
+
+// Fixed-order sums of column k (columns col_stride apart) over `count`
+// entries spaced `step` apart, split over Q threads per column (thread (k, j)
+// takes entries j, j+Q, ..),
+// then combined in j order through LDS.  Entries are read device-coherently:
+// they were written by other workgroups of this launch.  Every thread of the
+// workgroup must call this; out[k] receives the column sums.
+template <int K>
+__device__ __forceinline__ void column_sums(double* base, int col_stride, int count, int step,
+                                            double* lds, double* out) {
+  constexpr int Q = [] {
+    int q = 1;
+    while (q * 2 * K <= kBlock && q * 2 <= 16) q *= 2;
+    return q;
+  }();
+  const int tid = threadIdx.x;
+  if (tid < K * Q) {
+    const int k = tid / Q, j = tid % Q;
+    double* col = base + int64_t(k) * col_stride;
     double s = 0.0, comp = 0.0;
-    for (int t = lane; t < nt; t += 64) {  // Neumaier, tile order
-      const double x = colp[t];
-      const double u = s + x;
-      comp += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
-      s = u;
-    }
-    double v = s + comp;
+    int m = j;
+    for (; m + 7 * Q < count; m += 8 * Q) {  // eight loads in flight
+      double x[8];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) tot[k] = v;
-  }
-  if (!hit) {  // keep this point's constants for the next evaluation
-    const int nw = int(sizeof(ConstBlock) / sizeof(int));
-    const int* src = reinterpret_cast<const int*>(cb);
-    int* dst = reinterpret_cast<int*>(J.cst);
-    for (int i = tid; i < nw; i += kBlock) dst[i] = src[i];
+      for (int u = 0; u < 8; ++u)
+        x[u] = __hip_atomic_load(col + int64_t(m + u * Q) * step, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {  // Neumaier, in entry order
+        const double t = s + x[u];
+        comp += fabs(s) >= fabs(x[u]) ? (s - t) + x[u] : (x[u] - t) + s;
+        s = t;
+      }
+    }
+    for (; m < count; m += Q) {
+      const double xv =
+          __hip_atomic_load(col + int64_t(m) * step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double t = s + xv;
+      comp += fabs(s) >= fabs(xv) ? (s - t) + xv : (xv - t) + s;
+      s = t;
+    }
+    lds[k * Q + j] = s + comp;
   }
   __syncthreads();
-  if (tid == 0) {
-    epilogue(*J.plan, cb, tot, out_override ? out_override : J.out, tot + K);
-    atomicExch(J.counter, 0u);
+  if (tid < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) s += lds[tid * Q + j];
+    out[tid] = s;
   }
+  __syncthreads();
 }
 
 // Copies of wave-invariant values in scalar registers.
@@ -654,32 +681,6 @@ __device__ __forceinline__ double to_sgpr(double v) {
   const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(b & 0xffffffffu));
   const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(b >> 32));
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
-}
-
-// Stages the parameter-only constants of theta into s_cb (LDS).  The job keeps
-// the block of the last point it evaluated; when theta matches it bit for bit
-// the block is copied, otherwise the first lane computes it (the prologue:
-// normalisations, combined prefactors, angular coefficients, all in FP64).
-__device__ __forceinline__ void stage_constants(const Job& J, const double* __restrict__ th,
-                                                ConstBlock* s_cb, int* s_hit) {
-  const int tid = threadIdx.x;
-  if (tid < 64) {
-    const int npar = J.plan->npar;
-    const ConstBlock* g = J.cst;
-    bool eq = true;
-    if (tid < npar) eq = __double_as_longlong(th[tid]) == __double_as_longlong(g->theta[tid]);
-    const bool hit = __all(eq) && g->valid;
-    if (hit) {
-      const int nw = int(sizeof(ConstBlock) / sizeof(int));
-      const int* src = reinterpret_cast<const int*>(g);
-      int* dst = reinterpret_cast<int*>(s_cb);
-      for (int i = tid; i < nw; i += 64) dst[i] = src[i];
-    } else if (tid == 0) {
-      compute_constants(*J.plan, th, s_cb);
-    }
-    if (tid == 0) *s_hit = hit ? 1 : 0;
-  }
-  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -694,7 +695,7 @@ __host__ __device__ constexpr int reduce_parts() {
 }
 
 template <class S, class P>
-__global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jobs,
+__global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* __restrict__ jobs,
                                                       const int2* __restrict__ tmap,
                                                       const double* __restrict__ theta_override,
                                                       double* __restrict__ out_override) {
@@ -707,21 +708,39 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jo
     tile = t.y;
     if (jid < 0) return;
   }
-  const Job& J = jobs[jid];
-  __shared__ ConstBlock s_cb;
-  __shared__ int s_hit;
+  const Job J = tmap ? jobs[jid] : j0;
+  __shared__ __align__(16) ConstBlock s_cb;
   const double* __restrict__ th = (theta_override && !tmap) ? theta_override : J.theta;
-  stage_constants(J, th, &s_cb, &s_hit);
+  const int tid = threadIdx.x, lane = tid & 63;
+
+  // Parameter-only constants.  The job keeps the block of the last point it
+  // evaluated: when theta matches it bit for bit its constants are used
+  // (scalar loads, issued together with the comparison); otherwise the first
+  // lane computes them here in FP64 (the prologue: normalisations, combined
+  // prefactors, angular coefficients).
+  const ConstBlock* __restrict__ gc = J.cst;
   T c[S::ncst];
 #pragma unroll
-  for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
+  for (int i = 0; i < S::ncst; ++i) c[i] = P::consts(gc)[i];
   T xref[S::ndim];
 #pragma unroll
-  for (int d = 0; d < S::ndim; ++d) xref[d] = to_sgpr(P::xrefs(&s_cb)[d]);
+  for (int d = 0; d < S::ndim; ++d) xref[d] = P::xrefs(gc)[d];
+  bool eq = true;
+  if (lane < J.npar)
+    eq = __double_as_longlong(th[lane]) == __double_as_longlong(gc->theta[lane]);
+  const bool hit = __all(eq) && gc->valid;  // the same in every wave
+  if (!hit) {
+    if (tid == 0) compute_constants(*J.plan, th, &s_cb);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
+#pragma unroll
+    for (int d = 0; d < S::ndim; ++d) xref[d] = to_sgpr(P::xrefs(&s_cb)[d]);
+  }
+
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
-
   const int64_t tsize = int64_t(J.events_per_thread) * kBlock;
   const int64_t base = int64_t(tile) * tsize;
   const bool full = base + tsize <= J.n;
@@ -741,14 +760,14 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jo
   constexpr int STRIDE = kBlock + 8;
   constexpr int PARTS = reduce_parts<K>();
   constexpr int CH = kBlock / PARTS;
-  // T-sized transpose buffer, reused by pass 2 for K + UML_MAX_PARAMS doubles
-  constexpr int LDS_T = (K * STRIDE * sizeof(T) > (K + UML_MAX_PARAMS) * sizeof(double))
-                            ? K * STRIDE
-                            : int((K + UML_MAX_PARAMS) * sizeof(double) / sizeof(T)) + 1;
-  __shared__ T red[LDS_T];
-  __shared__ double red2[K * PARTS];
-  __shared__ int s_last;
-  const int tid = threadIdx.x;
+  // T-sized transpose buffer, reused afterwards for K + UML_MAX_PARAMS
+  // doubles followed by the plan
+  constexpr int PASS2_BYTES = (K + UML_MAX_PARAMS) * sizeof(double) + sizeof(Plan) + 16;
+  constexpr int LDS_T = (K * STRIDE * sizeof(T) > PASS2_BYTES) ? K * STRIDE
+                                                               : int(PASS2_BYTES / sizeof(T)) + 4;
+  __shared__ __align__(16) T red[LDS_T];
+  __shared__ double red2[K * (PARTS > 16 ? PARTS : 16)];
+  __shared__ int s_flag;
 #pragma unroll
   for (int k = 0; k < K; ++k) red[k * STRIDE + tid] = acc[k];
   __syncthreads();
@@ -760,32 +779,67 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job* __restrict__ jo
     red2[k * PARTS + p] = s;
   }
   __syncthreads();
+  const int nt = J.n_tiles;
+  double* gpart = J.partials + int64_t(K) * nt;  // [K][kGroups]
   if (tid < K) {
     double s = 0.0;
 #pragma unroll
     for (int p = 0; p < PARTS; ++p) s += red2[tid * PARTS + p];
-    J.partials[int64_t(tid) * J.n_tiles + tile] = s;
-    __threadfence();  // release the partial to the other workgroups
+    // device-coherent store: written through to the point where every XCD's
+    // loads of the same address meet, so no L2 write-back is needed
+    __hip_atomic_store(J.partials + int64_t(tid) * nt + tile, s, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
+  // Completion, in two levels (see kGroups).  The barrier before each
+  // counter step waits for this workgroup's coherent stores to complete.
+  const int ng = nt < kGroups ? nt : kGroups;
+  const int g = tile % ng;
   __syncthreads();
   if (tid == 0) {
-    const unsigned prev = atomicAdd(J.counter, 1u);
-    s_last = (prev + 1u == unsigned(J.n_tiles)) ? 1 : 0;
+    const unsigned members = unsigned((nt - 1 - g) / ng + 1);
+    unsigned* gcnt = J.counter + g * kCounterStride;
+    const unsigned p = __hip_atomic_fetch_add(gcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_flag = (p + 1u == members) ? 1 : 0;
+    if (s_flag) __hip_atomic_store(gcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();  // acquire every tile's partial
-  finalize(J, K, reinterpret_cast<double*>(red), &s_cb, s_hit, out_override);
+  if (!s_flag) return;
+  // the last tile of group g sums the group's tiles g, g + ng, .. in order
+  double* tot = reinterpret_cast<double*>(red);
+  {
+    const int members = (nt - 1 - g) / ng + 1;
+    column_sums<K>(J.partials + g, nt, members, ng, red2, tot);
+  }
+  if (tid < K)
+    __hip_atomic_store(gpart + int64_t(tid) * kGroups + g, tot[tid], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned* top = J.counter + kGroups * kCounterStride;
+    const unsigned q = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_flag = (q + 1u == unsigned(ng)) ? 1 : 0;
+    if (s_flag) __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (!s_flag) return;
+  // the last group: the plan, the constants to keep, the sum over groups
+  Plan* s_plan = reinterpret_cast<Plan*>(tot + ((K + UML_MAX_PARAMS + 1) & ~1));  // 16-byte aligned
+  bulk_copy16(s_plan, J.plan, int(sizeof(Plan)));
+  const ConstBlock* cb = hit ? gc : &s_cb;
+  if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
+  column_sums<K>(gpart, kGroups, ng, 1, red2, tot);
+  if (tid == 0)
+    epilogue(*s_plan, cb, tot, (out_override && !tmap) ? out_override : J.out, tot + K);
 }
 
 template <class S>
 void launch_eval(const LaunchArgs& a) {
   if (a.precision == UML_MIXED)
     hipLaunchKernelGGL((eval_kernel<S, PrecMixed>), dim3(a.grid), dim3(kBlock), 0, a.stream,
-                       a.jobs, a.tmap, a.theta, a.out);
+                       a.job0, a.jobs, a.tmap, a.theta, a.out);
   else
-    hipLaunchKernelGGL((eval_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream, a.jobs,
-                       a.tmap, a.theta, a.out);
+    hipLaunchKernelGGL((eval_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream,
+                       a.job0, a.jobs, a.tmap, a.theta, a.out);
 }
 
 template <class S>

@@ -9,7 +9,8 @@
 namespace uml {
 
 struct LaunchArgs {
-  const Job* jobs;       // device array of jobs
+  Job job0;              // the job of a single-dataset launch (by value)
+  const Job* jobs;       // device array of jobs (batched launches)
   const int2* tmap;      // workgroup -> (job, tile), or nullptr: job 0, tile = workgroup
   int grid;              // workgroups
   double* out;           // overrides jobs[0].out when not nullptr

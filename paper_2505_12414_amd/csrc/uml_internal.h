@@ -95,7 +95,9 @@ struct Plan {
   double lo[UML_MAX_DIMS], hi[UML_MAX_DIMS];  // per kernel dimension
   double xref[UML_MAX_DIMS];     // per kernel dimension (0: not shifted)
   int precision;
+  int pad_[3];
 };
+static_assert(sizeof(Plan) % 16 == 0, "Plan is copied in 16-byte units");
 
 // Parameter-dependent constants for one evaluation (written by the prologue).
 struct ConstBlock {
@@ -107,7 +109,9 @@ struct ConstBlock {
   float xf[UML_MAX_DIMS];   // the same in FP32 (exact: FP32 values)
   int domain_ok;        // 0 if theta is outside the model's domain
   int valid;            // 1 once written: theta[] is the key of this block
+  int pad_[2];
 };
+static_assert(sizeof(ConstBlock) % 16 == 0, "ConstBlock is copied in 16-byte units");
 
 // Device-resident state of one BFGS fit (one per job in fit mode).
 struct FitState {
@@ -136,13 +140,23 @@ struct Job {
   int32_t n_tiles;
   int32_t events_per_thread;      // E: events per thread per tile
   ConstBlock* cst;                // constants of the last evaluated point (cache)
-  double* partials;               // [K][n_tiles]
-  unsigned int* counter;          // last-workgroup counter
+  double* partials;               // [K][n_tiles] tile partials, then [K][kGroups] group partials
+  unsigned int* counter;          // completion counters: kGroups group counters
+                                  // and one global, each on its own 128-byte line
   double* out;                    // [1 + nfree]: nll, gradient
   const Plan* plan;               // device copy of the plan
   FitState* fit;                  // BFGS state (fit mode) or nullptr
   const double* theta;            // parameter vector to evaluate (device)
+  int32_t npar;                   // parameters in theta
 };
+
+// Completion counting: tile t reports to group counter t % kGroups; the last
+// tile of a group reports to the global counter.  Same-address device-scope
+// atomics serialise across the chip, so a single counter would cost one
+// round of that serialisation per tile.
+constexpr int kGroups = 64;
+constexpr int kCounterStride = 32;  // uints: one counter per 128-byte line
+constexpr int kCounterWords = (kGroups + 1) * kCounterStride;
 
 // Events per thread per tile for a dataset of n events: enough tiles to
 // fill the chip at 1e6 events, few enough partial sums at 1e7 and beyond.

@@ -135,6 +135,21 @@ SIGNATURES = {
 _lib = None
 
 
+def _preload_torch_hip_runtime():
+    """Loads the HIP runtime bundled with PyTorch before libuml, so that
+    libuml, torch's streams and torch's device memory share one runtime
+    (both runtimes carry the soname libamdhip64.so.7; the first one loaded
+    serves every later user in the process)."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return None
+    path = os.path.join(os.path.dirname(spec.origin), "lib", "libamdhip64.so")
+    if os.path.exists(path):
+        return C.CDLL(path, mode=C.RTLD_GLOBAL)
+    return None
+
+
 def lib():
     """The loaded libuml.so (raises if it has not been built)."""
     global _lib
@@ -142,6 +157,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2505_12414_amd.build` (no CPU fallback exists)")
+        _preload_torch_hip_runtime()
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
