@@ -169,10 +169,13 @@ struct Cheb {
 
 // P-wave angular density (Eq. 4) in dimensions (cos theta_l, cos theta_K, phi).
 // Written as  v = c0 u0 + c1 (u1 - u0) + sum_k c_{k+1} b_k  with
-//   u0 = sin^2 K (3/4 + cos 2l / 4),  u1 = cos^2 K (1 - cos 2l),
-//   b = {S3, S4, S5, AFB, S7, S8, S9 terms},
-// c = 9/(32 pi) * {1, FL, S3, S4, S5, AFB, S7, S8, S9};
-// moments m = {u1 - u0, b_S3, .., b_S9}.
+//   u0 = sin^2 K (3/4 + cos 2l / 4) = sin^2 K (1 - sin^2 l / 2),
+//   u1 = cos^2 K (1 - cos 2l) = 2 cos^2 K sin^2 l,
+//   b  = the S3, S4, S5, AFB, S7, S8, S9 terms without their constant
+//        factors (1, 4, 2, 4/3, 2, 4, 2), which the prologue folds into
+//        c = 9/(32 pi) * {1, FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8, 2 S9};
+// moments m = {u1 - u0, b_S3, .., b_S9}.  sin K sin l = sqrt(sin^2 K sin^2 l)
+// needs one square root; 1 - c^2 is one FMA (correctly rounded).
 template <int D0, int D1, int D2>
 struct PWave {
   static constexpr int kind = FK_PWAVE, order = 0;
@@ -186,24 +189,23 @@ struct PWave {
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
     const T cl = xs[D0], ck = xs[D1], ph = xs[D2];
-    const T sl2 = (T(1) - cl) * (T(1) + cl);  // sin^2 theta_l
-    const T sk2 = (T(1) - ck) * (T(1) + ck);  // sin^2 theta_K
-    const T sl = k_sqrt(sl2), sk = k_sqrt(sk2);
+    const T sl2 = fma(-cl, cl, T(1));  // sin^2 theta_l
+    const T sk2 = fma(-ck, ck, T(1));  // sin^2 theta_K
+    const T skl2 = sk2 * sl2;
+    const T skl = k_sqrt(skl2);        // sin theta_K sin theta_l
     T sp, cp;
     k_sincos(ph, sp, cp);
-    const T u0 = sk2 * fma(T(-0.5), sl2, T(1));
-    const T u1 = T(2) * ck * ck * sl2;
-    const T skl2 = sk2 * sl2;
-    const T s2k_sl = T(2) * sk * ck * sl;        // sin 2K sin l
-    const T s2k_s2l = T(2) * s2k_sl * cl;        // sin 2K sin 2l
-    m[0] = u1 - u0;
-    m[1] = skl2 * ((cp - sp) * (cp + sp));       // S3: sin^2K sin^2l cos 2phi
-    m[2] = s2k_s2l * cp;                         // S4
-    m[3] = s2k_sl * cp;                          // S5
-    m[4] = T(4.0 / 3.0) * sk2 * cl;              // AFB
-    m[5] = s2k_sl * sp;                          // S7
-    m[6] = s2k_s2l * sp;                         // S8
-    m[7] = skl2 * (T(2) * sp * cp);              // S9: sin^2K sin^2l sin 2phi
+    const T w = ck * skl;              // sin 2K sin l / 2
+    const T wc = w * cl;               // sin 2K sin 2l / 4
+    const T u0 = fma(T(-0.5), skl2, sk2);
+    m[0] = fma((ck + ck) * ck, sl2, -u0);  // u1 - u0
+    m[1] = skl2 * fma(cp + cp, cp, T(-1)); // S3: sin^2K sin^2l cos 2phi
+    m[2] = wc * cp;                        // S4 / 4
+    m[3] = w * cp;                         // S5 / 2
+    m[4] = sk2 * cl;                       // AFB / (4/3)
+    m[5] = w * sp;                         // S7 / 2
+    m[6] = wc * sp;                        // S8 / 4
+    m[7] = skl2 * (sp * cp);               // S9 / 2
     T val = c[0] * u0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) val = fma(c[1 + k], m[k], val);
@@ -464,9 +466,11 @@ __device__ __noinline__ double d_exp_h(double z) {
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kSqrt2Pi = 2.5066282746310005024;
 
-// Gaussian normalised on [a, b] (Eq. 2): constants of the kernel, epilogue
-// derivatives of its log-normalisation, and log2 of its prefactor
+// Gaussian normalised on [a, b] (Eq. 2): constants of the kernel, the
+// epilogue coefficients of its gradient terms, and log2 of its prefactor
 // 1 / (sigma sqrt(2 pi) (Phi(zb) - Phi(za))).
+//   d ln g / d mu    = d / sigma^2 - (phi(za) - phi(zb)) / (sigma D)
+//   d ln g / d sigma = d^2 / sigma^3 - 1/sigma - (za phi(za) - zb phi(zb)) / (sigma D)
 __device__ __noinline__ bool gauss_constants(const FactorPlan& F, const double* __restrict__ th,
                                              double* kc, double* ec, double* lnorm2) {
   const double a = F.lo[0], b = F.hi[0];
@@ -477,34 +481,37 @@ __device__ __noinline__ bool gauss_constants(const FactorPlan& F, const double* 
   kc[0] = mu - F.xref;
   kc[1] = kLog2e / (2.0 * sg * sg);
   *lnorm2 = -nl_log2(sg * kSqrt2Pi * D);
-  ec[0] = 1.0 / (sg * sg);                              // d ln g / d mu = d/sigma^2 - ec[1]
-  ec[1] = (pa - pb) / (sg * D);
-  ec[2] = 1.0 / (sg * sg * sg);                         // d ln g / d sigma = d^2/sigma^3 - ec[3]
-  ec[3] = 1.0 / sg + (za * pa - zb * pb) / (sg * D);
+  ec[0] = 1.0 / (sg * sg);                           // x sum r d
+  ec[1] = -(pa - pb) / (sg * D);                     // x sum r
+  ec[2] = 1.0 / (sg * sg * sg);                      // x sum r d^2
+  ec[3] = -(1.0 / sg + (za * pa - zb * pb) / (sg * D));  // x sum r
   return sg > 0.0;
 }
 
 // Exponential e^{lambda x} normalised on [a, b] (Eq. 2), evaluated as
 // 2^{lambda log2(e) x'} with x' = x - xref; the prefactor e^{lambda xref}/N
 // is written through expm1 so that small |lambda| keeps full precision.
+//   d ln p / d lambda = x' - (E[x] - xref)
 __device__ __noinline__ bool exp_constants(const FactorPlan& F, const double* __restrict__ th,
                                            double* kc, double* ec, double* lnorm2) {
   const double a = F.lo[0], b = F.hi[0], xr = F.xref, L = b - a;
   const double lam = th[F.par[0]];
   kc[0] = lam * kLog2e;
+  ec[0] = 1.0;
   if (lam == 0.0) {
     *lnorm2 = -nl_log2(L);
-    ec[0] = a + 0.5 * L - xr;                           // E[x] - xref
+    ec[1] = -(a + 0.5 * L - xr);
   } else {
     const double z = lam * L;
     *lnorm2 = (lam * (xr - a) - nl_log(nl_expm1(z) / lam)) * kLog2e;
-    ec[0] = a - xr + L * d_exp_h(z);
+    ec[1] = -(a - xr + L * d_exp_h(z));
   }
   return true;
 }
 
 // Chebyshev series 1 + sum_j c_j T_j(u) on [a, b], u = (2x - a - b)/(b - a),
 // with norm N_C = (b - a) + sum_{j even} c_j (b - a)/(1 - j^2).
+//   d ln p / d c_j = T_j / (1 + sum c T) - J_j / N_C,  J_j = d N_C / d c_j
 __device__ __noinline__ bool cheb_constants(const FactorPlan& F, const double* __restrict__ th,
                                             double* kc, double* ec) {
   const double a = F.lo[0], b = F.hi[0], xr = F.xref;
@@ -513,23 +520,30 @@ __device__ __noinline__ bool cheb_constants(const FactorPlan& F, const double* _
   for (int jj = 1; jj <= k; ++jj) {
     const double J = (jj % 2 == 0) ? (b - a) / (1.0 - double(jj * jj)) : 0.0;
     N += th[F.par[jj - 1]] * J;
-    ec[jj] = J;
+    ec[k + jj - 1] = J;
   }
   kc[0] = 2.0 / (b - a);
   kc[1] = (2.0 * xr - a - b) / (b - a);
   kc[2] = 1.0 / N;
-  for (int jj = 1; jj <= k; ++jj) kc[2 + jj] = th[F.par[jj - 1]] / N;
-  ec[0] = 1.0 / N;
+  for (int jj = 1; jj <= k; ++jj) {
+    kc[2 + jj] = th[F.par[jj - 1]] / N;
+    ec[jj - 1] = 1.0 / N;                      // x sum q T_j
+    ec[k + jj - 1] = -ec[k + jj - 1] / N;      // x sum r
+  }
   return true;
 }
 
-// P-wave density (Eq. 4): coefficients 9/(32 pi) {1, FL, S3, .., S9}.
+// P-wave density (Eq. 4): coefficients 9/(32 pi) {1, FL, S3, 4 S4, 2 S5,
+// 4/3 AFB, 2 S7, 4 S8, 2 S9}; d ln A / d S_k = 9/(32 pi) s_k b_k / A.
 __device__ __noinline__ void pwave_constants(const FactorPlan& F, const double* __restrict__ th,
                                              double* kc, double* ec) {
   const double kap = 9.0 / (32.0 * M_PI);
+  const double scale[8] = {1.0, 1.0, 4.0, 2.0, 4.0 / 3.0, 2.0, 4.0, 2.0};
   kc[0] = kap;
-  for (int k = 0; k < 8; ++k) kc[1 + k] = kap * th[F.par[k]];
-  ec[0] = kap;
+  for (int k = 0; k < 8; ++k) {
+    kc[1 + k] = kap * scale[k] * th[F.par[k]];
+    ec[k] = kap * scale[k];
+  }
 }
 
 // The prologue: every parameter-only term of the point theta (Sec. 2.4.1).
@@ -544,6 +558,7 @@ __device__ __noinline__ void compute_constants(const Plan& P, const double* __re
       const double f = th[C.frac_par[k]];
       if (!(f >= 0.0 && f <= 1.0)) ok = false;
       lk2 += nl_log2(C.frac_sign[k] > 0 ? f : 1.0 - f);
+      cb->e[C.frac_ec[k]] = C.frac_sign[k] > 0 ? 1.0 / f : -1.0 / (1.0 - f);  // d ln F_c / d f
     }
     for (int j = 0; j < C.nfac; ++j) {
       const FactorPlan& F = P.fac[C.fac[j]];
@@ -570,45 +585,22 @@ __device__ __noinline__ void compute_constants(const Plan& P, const double* __re
   cb->valid = 1;
 }
 
-// NLL and gradient from the K moment sums (chain rule through the mixture).
-// g: UML_MAX_PARAMS doubles of scratch (LDS).
-__device__ __noinline__ void epilogue(const Plan& P, const ConstBlock* cb,
-                                      const double* __restrict__ tot, double* __restrict__ out,
-                                      double* __restrict__ g) {
-  for (int i = 0; i < P.npar; ++i) g[i] = 0.0;
-  const double* th = cb->theta;
-  const double nll = -0.69314718055994530942 * tot[0];
-  for (int ci = 0; ci < P.ncomp; ++ci) {
-    const CompPlan& C = P.comp[ci];
-    const double R = tot[C.slot_r];
-    for (int k = 0; k < C.nfrac; ++k) {
-      const int p = C.frac_par[k];
-      g[p] -= C.frac_sign[k] > 0 ? R / th[p] : -R / (1.0 - th[p]);
-    }
-    for (int j = 0; j < C.nfac; ++j) {
-      const FactorPlan& F = P.fac[C.fac[j]];
-      const double* ec = cb->e + F.ecst;
-      const double* M = tot + F.mom;
-      switch (F.kind) {
-        case FK_GAUSS:
-          g[F.par[0]] -= M[0] * ec[0] - R * ec[1];
-          g[F.par[1]] -= M[1] * ec[2] - R * ec[3];
-          break;
-        case FK_EXP:
-          g[F.par[0]] -= M[0] - R * ec[0];
-          break;
-        case FK_CHEB:
-          for (int jj = 0; jj < F.order; ++jj) g[F.par[jj]] -= (M[jj] - R * ec[1 + jj]) * ec[0];
-          break;
-        case FK_PWAVE:
-          for (int k = 0; k < 8; ++k) g[F.par[k]] -= ec[0] * M[k];
-          break;
-      }
-    }
-  }
+// NLL and gradient from the K moment sums: the chain rule through the
+// mixture reduces to d NLL / d theta_p = -sum over p's terms of
+// e[ec] * M[mom] (EpiTerm), one thread per free parameter.
+__device__ __forceinline__ void epilogue(const Plan& P, const ConstBlock* cb,
+                                         const double* __restrict__ tot, double* __restrict__ out) {
+  const int tid = threadIdx.x;
+  const double nll = -0.69314718055994530942 * tot[0];  // slot 0 holds sum w log2 P
   const bool bad = !cb->domain_ok || !isfinite(nll);
-  out[0] = bad ? INFINITY : nll;
-  for (int i = 0; i < P.nfree; ++i) out[1 + i] = bad ? 0.0 : g[P.free_idx[i]];
+  if (tid == 0) out[0] = bad ? INFINITY : nll;
+  if (tid < P.nfree) {
+    const int p = P.free_idx[tid];
+    double g = 0.0;
+    for (int t = P.term_begin[p]; t < P.term_begin[p + 1]; ++t)
+      g -= cb->e[P.term[t].ec] * tot[P.term[t].mom];
+    out[1 + tid] = bad ? 0.0 : g;
+  }
 }
 
 // Bulk copy of n bytes (a multiple of 16, both 16-byte aligned) by the
@@ -781,20 +773,25 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   __syncthreads();
   const int nt = J.n_tiles;
   double* gpart = J.partials + int64_t(K) * nt;  // [K][kGroups]
+  // With at most kGroups tiles each tile is its own group: its partial goes
+  // straight to the group partials and the group level is skipped.
+  const bool single = nt <= kGroups;
   if (tid < K) {
     double s = 0.0;
 #pragma unroll
     for (int p = 0; p < PARTS; ++p) s += red2[tid * PARTS + p];
     // device-coherent store: written through to the point where every XCD's
     // loads of the same address meet, so no L2 write-back is needed
-    __hip_atomic_store(J.partials + int64_t(tid) * nt + tile, s, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    double* dst = single ? gpart + int64_t(tid) * kGroups + tile : J.partials + int64_t(tid) * nt + tile;
+    __hip_atomic_store(dst, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // Completion, in two levels (see kGroups).  The barrier before each
   // counter step waits for this workgroup's coherent stores to complete.
   const int ng = nt < kGroups ? nt : kGroups;
   const int g = tile % ng;
+  double* tot = reinterpret_cast<double*>(red);
   __syncthreads();
+  if (single) goto top_level;
   if (tid == 0) {
     const unsigned members = unsigned((nt - 1 - g) / ng + 1);
     unsigned* gcnt = J.counter + g * kCounterStride;
@@ -805,7 +802,6 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   __syncthreads();
   if (!s_flag) return;
   // the last tile of group g sums the group's tiles g, g + ng, .. in order
-  double* tot = reinterpret_cast<double*>(red);
   {
     const int members = (nt - 1 - g) / ng + 1;
     column_sums<K>(J.partials + g, nt, members, ng, red2, tot);
@@ -814,6 +810,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
     __hip_atomic_store(gpart + int64_t(tid) * kGroups + g, tot[tid], __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
+top_level:
   if (tid == 0) {
     unsigned* top = J.counter + kGroups * kCounterStride;
     const unsigned q = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -828,8 +825,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   const ConstBlock* cb = hit ? gc : &s_cb;
   if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
   column_sums<K>(gpart, kGroups, ng, 1, red2, tot);
-  if (tid == 0)
-    epilogue(*s_plan, cb, tot, (out_override && !tmap) ? out_override : J.out, tot + K);
+  epilogue(*s_plan, cb, tot, (out_override && !tmap) ? out_override : J.out);
 }
 
 template <class S>

@@ -291,6 +291,10 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
   }
 
   // layout
+  struct T3 {
+    int par, mom, ec;
+  };
+  std::vector<T3> gterms;
   P.ncomp = (int)terms.size();
   int cst = 0, ecst = 0, mom = 1;
   for (int c = 0; c < P.ncomp; ++c) {
@@ -301,12 +305,14 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
       return UML_E_UNSUPPORTED;
     }
     C.nfrac = (int)t.frac.size();
+    C.cst_lk2 = cst++;
+    C.slot_r = mom++;
     for (int k = 0; k < C.nfrac; ++k) {
       C.frac_par[k] = t.frac[k].first;
       C.frac_sign[k] = t.frac[k].second;
+      C.frac_ec[k] = ecst++;
+      gterms.push_back({C.frac_par[k], C.slot_r, C.frac_ec[k]});
     }
-    C.cst_lk2 = cst++;
-    C.slot_r = mom++;
     C.nfac = (int)t.leaves.size();
     for (int j = 0; j < C.nfac; ++j) {
       if (P.nfac >= kMaxFac) {
@@ -327,6 +333,28 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
       F.cst = cst;
       F.ecst = ecst;
       F.mom = mom;
+      // gradient terms (see EpiTerm); R = the component's responsibility sum
+      switch (F.kind) {
+        case FK_GAUSS:  // mu: M_d, R; sigma: M_dd, R
+          gterms.push_back({F.par[0], mom, ecst});
+          gterms.push_back({F.par[0], C.slot_r, ecst + 1});
+          gterms.push_back({F.par[1], mom + 1, ecst + 2});
+          gterms.push_back({F.par[1], C.slot_r, ecst + 3});
+          break;
+        case FK_EXP:
+          gterms.push_back({F.par[0], mom, ecst});
+          gterms.push_back({F.par[0], C.slot_r, ecst + 1});
+          break;
+        case FK_CHEB:
+          for (int k = 0; k < F.order; ++k) {
+            gterms.push_back({F.par[k], mom + k, ecst + k});
+            gterms.push_back({F.par[k], C.slot_r, ecst + F.order + k});
+          }
+          break;
+        case FK_PWAVE:
+          for (int k = 0; k < 8; ++k) gterms.push_back({F.par[k], mom + k, ecst + k});
+          break;
+      }
       cst += fk_ncst(F.kind, F.order);
       ecst += fk_necst(F.kind, F.order);
       mom += fk_nmom(F.kind, F.order);
@@ -341,6 +369,20 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
   P.necst = ecst;
   P.K = mom;
   P.npar = d->n_params;
+  if ((int)gterms.size() > kMaxTerms) {
+    err = "model too large for the gradient term table";
+    return UML_E_UNSUPPORTED;
+  }
+  std::stable_sort(gterms.begin(), gterms.end(), [](const T3& a, const T3& b) { return a.par < b.par; });
+  P.nterm = (int)gterms.size();
+  for (int k = 0; k < P.nterm; ++k) {
+    P.term[k].mom = (short)gterms[k].mom;
+    P.term[k].ec = (short)gterms[k].ec;
+  }
+  for (int p = 0, k = 0; p <= P.npar; ++p) {
+    while (k < P.nterm && gterms[k].par < p) ++k;
+    P.term_begin[p] = k;
+  }
   P.nfree = 0;
   for (int k = 0; k < d->n_params; ++k) {
     P.free_pos[k] = -1;

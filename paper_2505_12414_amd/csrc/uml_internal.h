@@ -51,7 +51,7 @@ __host__ __device__ constexpr int fk_nmom(int kind, int order) {
   return kind == FK_GAUSS ? 2 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order : 8;
 }
 __host__ __device__ constexpr int fk_necst(int kind, int order) {
-  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order + 1 : 1;
+  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 2 : kind == FK_CHEB ? 2 * order : 8;
 }
 __host__ __device__ constexpr bool fk_expo(int kind) {
   return kind == FK_GAUSS || kind == FK_EXP;
@@ -74,9 +74,18 @@ struct CompPlan {
   int nfrac;
   int frac_par[8];          // SUM fraction parameters on the path
   int frac_sign[8];         // +1: f, -1: 1 - f
+  int frac_ec[8];           // epilogue constant d ln F_c / d f of each entry
   int cst_lk2;              // offset of log2 K_c
   int slot_r;               // moment slot of r_c
 };
+
+// One term of the gradient: d NLL / d theta_p = -sum_t e[ec_t] * M[mom_t]
+// over the terms of parameter p (e: epilogue constants of the point,
+// M: the moment sums).
+struct EpiTerm {
+  short mom, ec;
+};
+constexpr int kMaxTerms = 128;
 
 struct Plan {
   int ncomp;
@@ -95,7 +104,10 @@ struct Plan {
   double lo[UML_MAX_DIMS], hi[UML_MAX_DIMS];  // per kernel dimension
   double xref[UML_MAX_DIMS];     // per kernel dimension (0: not shifted)
   int precision;
-  int pad_[3];
+  int nterm;
+  EpiTerm term[kMaxTerms];              // grouped by parameter
+  int term_begin[UML_MAX_PARAMS + 1];   // terms of parameter p: [begin[p], begin[p+1])
+  int pad_[1];
 };
 static_assert(sizeof(Plan) % 16 == 0, "Plan is copied in 16-byte units");
 
