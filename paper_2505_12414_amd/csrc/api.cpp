@@ -51,11 +51,16 @@ int uml_model_create(const uml_model_desc* desc, uml_model** out) {
     delete m;
     return set_error(UML_E_INVALID, "uml_model_create: internal layout mismatch for " + sig);
   }
+  const bool have_hess = build_hess_plan(m->plan, m->hplan, m->hess_err);
   hipError_t e = hipGetDevice(&m->device);
   if (e == hipSuccess) e = hipMalloc(&m->d_plan, sizeof(Plan));
   if (e == hipSuccess) e = hipMemcpy(m->d_plan, &m->plan, sizeof(Plan), hipMemcpyHostToDevice);
+  if (e == hipSuccess && have_hess) e = hipMalloc(&m->d_hplan, sizeof(HessPlan));
+  if (e == hipSuccess && have_hess)
+    e = hipMemcpy(m->d_hplan, &m->hplan, sizeof(HessPlan), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (m->d_plan) (void)hipFree(m->d_plan);
+    if (m->d_hplan) (void)hipFree(m->d_hplan);
     delete m;
     return set_error(UML_E_HIP, std::string("uml_model_create: ") + hipGetErrorString(e));
   }
@@ -66,6 +71,7 @@ int uml_model_create(const uml_model_desc* desc, uml_model** out) {
 void uml_model_destroy(uml_model* m) {
   if (!m) return;
   if (m->d_plan) (void)hipFree(m->d_plan);
+  if (m->d_hplan) (void)hipFree(m->d_hplan);
   delete m;
 }
 
@@ -218,7 +224,7 @@ void uml_data_destroy(uml_data* d) {
   if (!d) return;
   if (d->d_events) (void)hipFree(d->d_events);
   if (d->d_work) (void)hipFree(d->d_work);
-  if (d->d_hess_part) (void)hipFree(d->d_hess_part);
+  if (d->d_hwork) (void)hipFree(d->d_hwork);
   if (d->h_stage) (void)hipHostFree(d->h_stage);
   delete d;
 }

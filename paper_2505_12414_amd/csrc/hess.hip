@@ -1,0 +1,320 @@
+// Hessian of the NLL on gfx950: H = sum_i w_i (s_i s_i^T - d2P_i / P_i)
+// (the second derivatives of Sec. 2.2, used for the covariance the HESSE
+// step reports), together with the NLL, its gradient and, for weighted
+// fits, W2 = sum_i w_i^2 s_i s_i^T (the middle of the sandwich covariance).
+//
+// With P = sum_c S_c, S_c = F_c prod_f p_f, responsibilities r_c = S_c / P
+// and component log-derivatives l_c = d ln S_c / d theta:
+//     s = sum_c r_c l_c,     d2P / P = sum_c r_c (d2 S_c / S_c),
+// and (d2 S_c / S_c)_ab is l_ca l_cb when a and b belong to different units
+// of the component (different factors, or a fraction and a factor), and the
+// unit's own d2p/p when they belong to the same one (zero for a fraction and
+// for the P-wave density, which are linear in their parameters).
+//
+// One workgroup per tile of events.  The tile is processed in chunks: each
+// lane of the first wave evaluates one event by walking the plan and stages
+// (w, log2 P, s, r, l, d2p/p) in LDS; then each thread owns a few of the
+// M = 1 + nfree + 2 npairs sums and accumulates them in FP64 over the chunk in
+// event order.  Tile sums go to [M][n_tiles]; a second kernel adds the tiles
+// in tile order.  Every order is fixed: the results are reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "devmath.h"
+#include "hess.h"
+#include "prologue.h"
+#include "uml_internal.h"
+
+namespace uml {
+
+// Second derivatives that the gradient does not need: d2 ln D of the
+// Gaussian normalisation D = Phi(zb) - Phi(za) in (mu, sigma), and -Var[x]
+// of the truncated exponential (d2 ln p / d lambda^2).
+static __device__ __noinline__ void hess_constants(const Plan& P, const double* __restrict__ th,
+                                                   double* hc) {
+  const double kInvSqrt2Pi = 0.39894228040143267794;
+  for (int f = 0; f < P.nfac; ++f) {
+    const FactorPlan& F = P.fac[f];
+    double* h = hc + 4 * f;
+    h[0] = h[1] = h[2] = h[3] = 0.0;
+    const double a = F.lo[0], b = F.hi[0];
+    if (F.kind == FK_GAUSS) {
+      const double mu = th[F.par[0]], sg = th[F.par[1]];
+      const double za = (a - mu) / sg, zb = (b - mu) / sg;
+      const double D = d_phi_diff(za, zb);
+      const double pa = nl_exp(-0.5 * za * za) * kInvSqrt2Pi, pb = nl_exp(-0.5 * zb * zb) * kInvSqrt2Pi;
+      const double s2 = sg * sg;
+      const double Dm = (pa - pb) / sg, Ds = (za * pa - zb * pb) / sg;
+      const double Dmm = (za * pa - zb * pb) / s2;
+      const double Dms = (-(pa - pb) + za * za * pa - zb * zb * pb) / s2;
+      const double Dss = (-2.0 * za * pa + za * za * za * pa + 2.0 * zb * pb - zb * zb * zb * pb) / s2;
+      h[0] = Dmm / D - Dm * Dm / (D * D);
+      h[1] = Dms / D - Dm * Ds / (D * D);
+      h[2] = Dss / D - Ds * Ds / (D * D);
+    } else if (F.kind == FK_EXP) {
+      const double lam = th[F.par[0]], L = b - a, z = lam * L;
+      double hp;  // h'(z), h(z) = 1/(1 - e^{-z}) - 1/z; Var[x] = L^2 h'(lambda L)
+      if (fabs(z) < 0.05) {
+        const double z2 = z * z;
+        hp = 1.0 / 12.0 + z2 * (-1.0 / 240.0 + z2 * (1.0 / 6048.0 - z2 / 172800.0));
+      } else {
+        const double em = nl_expm1(-z);
+        hp = 1.0 / (z * z) - nl_exp(-z) / (em * em);
+      }
+      h[0] = -L * L * hp;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void hess_prologue_kernel(const Plan* __restrict__ plan,
+                                                           const double* __restrict__ theta,
+                                                           ConstBlock* cb, double* hc) {
+  if (threadIdx.x != 0) return;
+  compute_constants(*plan, theta, cb);
+  hess_constants(*plan, theta, hc);
+}
+
+template <class T>
+__device__ __forceinline__ T ld(const void* col, int64_t i) {
+  return static_cast<const T*>(col)[i];
+}
+
+// Evaluates one event and writes its staged row.
+template <class T>
+__device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& cb,
+                           const double* hc, const HessPlan& H, int64_t i, T* row) {
+  const int nf = P.nfree, nc = P.ncomp;
+  T* s = row + 2;
+  T* r = s + nf;
+  T* lv = r + nc;
+  T* q = lv + nc * nf;
+  for (int k = 0; k < nc * nf; ++k) lv[k] = T(0);
+  T E[kMaxComp], V[kMaxComp];
+  for (int c = 0; c < nc; ++c) {
+    const CompPlan& C = P.comp[c];
+    T* l = lv + c * nf;
+    T e = T(cb.d[C.cst_lk2]);
+    T v = T(1);
+    for (int k = 0; k < C.nfrac; ++k) {
+      const int fp = P.free_pos[C.frac_par[k]];
+      if (fp >= 0) l[fp] += T(cb.e[C.frac_ec[k]]);
+    }
+    for (int j = 0; j < C.nfac; ++j) {
+      const int fi = C.fac[j];
+      const FactorPlan& F = P.fac[fi];
+      const double* kc = cb.d + F.cst;
+      const double* ec = cb.e + F.ecst;
+      T* qf = q + H.q_off[fi];
+      switch (F.kind) {
+        case FK_GAUSS: {
+          const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
+          const T d = x - T(kc[0]);
+          e = fma(-d * d, T(kc[1]), e);
+          const T lm = fma(d, T(ec[0]), T(ec[1]));
+          const T ls = fma(d * d, T(ec[2]), T(ec[3]));
+          const int pm = P.free_pos[F.par[0]], ps = P.free_pos[F.par[1]];
+          if (pm >= 0) l[pm] += lm;
+          if (ps >= 0) l[ps] += ls;
+          const T is2 = T(ec[0]), is3 = T(ec[2]);
+          qf[0] = lm * lm - is2 - T(hc[4 * fi + 0]);
+          qf[1] = lm * ls - T(2) * d * is3 - T(hc[4 * fi + 1]);
+          qf[2] = ls * ls - T(3) * d * d * is2 * is2 + is2 - T(hc[4 * fi + 2]);
+          break;
+        }
+        case FK_EXP: {
+          const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
+          e = fma(x, T(kc[0]), e);
+          const T lx = x + T(ec[1]);
+          const int p = P.free_pos[F.par[0]];
+          if (p >= 0) l[p] += lx;
+          qf[0] = lx * lx + T(hc[4 * fi + 0]);
+          break;
+        }
+        case FK_CHEB: {
+          const int k = F.order;
+          const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
+          const T u = fma(x, T(kc[0]), T(kc[1]));
+          T tj[kMaxCheb + 1];
+          tj[0] = T(1);
+          tj[1] = u;
+          for (int jj = 2; jj <= k; ++jj) tj[jj] = T(2) * u * tj[jj - 1] - tj[jj - 2];
+          T val = T(kc[2]);
+          for (int jj = 1; jj <= k; ++jj) val = fma(T(kc[2 + jj]), tj[jj], val);
+          v *= val;
+          const T iv = T(1) / val;
+          for (int jj = 0; jj < k; ++jj) {
+            const int p = P.free_pos[F.par[jj]];
+            if (p >= 0) l[p] += fma(T(ec[jj]) * tj[jj + 1], iv, T(ec[k + jj]));
+          }
+          int t = 0;
+          for (int a = 0; a < k; ++a)
+            for (int b = a; b < k; ++b, ++t)
+              qf[t] = T(ec[0]) * iv * (tj[a + 1] * T(ec[k + b]) + tj[b + 1] * T(ec[k + a])) +
+                      T(2) * T(ec[k + a]) * T(ec[k + b]);
+          break;
+        }
+        case FK_PWAVE: {
+          const T cl = ld<T>(A.col[F.dim[0]], i), ck = ld<T>(A.col[F.dim[1]], i),
+                  ph = ld<T>(A.col[F.dim[2]], i);
+          const T sl2 = fma(-cl, cl, T(1)), sk2 = fma(-ck, ck, T(1));
+          const T skl2 = sk2 * sl2, skl = k_sqrt(skl2);
+          T sp, cp;
+          k_sincos(ph, sp, cp);
+          const T w = ck * skl, wc = w * cl;
+          const T u0 = fma(T(-0.5), skl2, sk2);
+          T m[8];
+          m[0] = fma((ck + ck) * ck, sl2, -u0);
+          m[1] = skl2 * fma(cp + cp, cp, T(-1));
+          m[2] = wc * cp;
+          m[3] = w * cp;
+          m[4] = sk2 * cl;
+          m[5] = w * sp;
+          m[6] = wc * sp;
+          m[7] = skl2 * (sp * cp);
+          T val = T(kc[0]) * u0;
+          for (int kk = 0; kk < 8; ++kk) val = fma(T(kc[1 + kk]), m[kk], val);
+          v *= val;
+          const T iv = T(1) / val;
+          for (int kk = 0; kk < 8; ++kk) {
+            const int p = P.free_pos[F.par[kk]];
+            if (p >= 0) l[p] += T(ec[kk]) * m[kk] * iv;
+          }
+          break;
+        }
+      }
+    }
+    E[c] = e;
+    V[c] = v;
+  }
+  T Emax = E[0];
+  for (int c = 1; c < nc; ++c) Emax = fmax(Emax, E[c]);
+  T Sp[kMaxComp], sum = T(0);
+  for (int c = 0; c < nc; ++c) {
+    Sp[c] = k_exp2(E[c] - Emax) * V[c];
+    sum += Sp[c];
+  }
+  const T inv = T(1) / sum;
+  row[1] = Emax + k_log2(sum);
+  for (int c = 0; c < nc; ++c) r[c] = Sp[c] * inv;
+  for (int a = 0; a < nf; ++a) {
+    T sa = T(0);
+    for (int c = 0; c < nc; ++c) sa = fma(r[c], lv[c * nf + a], sa);
+    s[a] = sa;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void hess_kernel(const HessArgs A) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  Plan* sP = reinterpret_cast<Plan*>(lds_raw);
+  ConstBlock* sC = reinterpret_cast<ConstBlock*>(lds_raw + sizeof(Plan));
+  HessPlan* sH = reinterpret_cast<HessPlan*>(lds_raw + sizeof(Plan) + sizeof(ConstBlock));
+  double* sh = reinterpret_cast<double*>(lds_raw + sizeof(Plan) + sizeof(ConstBlock) + sizeof(HessPlan));
+  T* stage = reinterpret_cast<T*>(sh + 4 * kMaxFac);
+  const int tid = threadIdx.x;
+  {
+    const int4* src = reinterpret_cast<const int4*>(A.plan);
+    int4* dst = reinterpret_cast<int4*>(sP);
+    for (int k = tid; k < int(sizeof(Plan) / 16); k += kBlock) dst[k] = src[k];
+    src = reinterpret_cast<const int4*>(A.cb);
+    dst = reinterpret_cast<int4*>(sC);
+    for (int k = tid; k < int(sizeof(ConstBlock) / 16); k += kBlock) dst[k] = src[k];
+    src = reinterpret_cast<const int4*>(A.hplan);
+    dst = reinterpret_cast<int4*>(sH);
+    for (int k = tid; k < int(sizeof(HessPlan) / 16); k += kBlock) dst[k] = src[k];
+    for (int k = tid; k < 4 * kMaxFac; k += kBlock) sh[k] = A.hc[k];
+  }
+  __syncthreads();
+  const Plan& P = *sP;
+  const HessPlan& H = *sH;
+  const int nf = P.nfree, nc = P.ncomp, V = A.row_len, M = A.n_sums;
+  double acc[kHessSumsPerThread];
+  for (int k = 0; k < kHessSumsPerThread; ++k) acc[k] = 0.0;
+  const int64_t t0 = int64_t(blockIdx.x) * A.tile_events;
+  const int64_t t1 = t0 + A.tile_events < A.n ? t0 + A.tile_events : A.n;
+  for (int64_t c0 = t0; c0 < t1; c0 += A.chunk) {
+    const int cnt = int((t1 - c0) < A.chunk ? (t1 - c0) : A.chunk);
+    if (tid < cnt) {
+      T* row = stage + int64_t(tid) * V;
+      row[0] = A.w ? ld<T>(A.w, c0 + tid) : T(1);
+      hess_event<T>(A, P, *sC, sh, H, c0 + tid, row);
+    }
+    __syncthreads();
+    for (int k = 0; k < kHessSumsPerThread; ++k) {
+      const int j = tid + k * kBlock;
+      if (j >= M) break;
+      double sacc = 0.0;
+      if (j == 0) {
+        for (int e = 0; e < cnt; ++e) sacc += double(stage[e * V]) * double(stage[e * V + 1]);
+      } else if (j <= nf) {
+        for (int e = 0; e < cnt; ++e) sacc += double(stage[e * V]) * double(stage[e * V + 2 + j - 1]);
+      } else {
+        const int pr = (j - 1 - nf) % H.npairs;
+        const bool w2 = (j - 1 - nf) >= H.npairs;
+        const int a = H.pa[pr], b = H.pb[pr];
+        const signed char* rel = H.rel + pr * kMaxComp;
+        for (int e = 0; e < cnt; ++e) {
+          const T* row = stage + e * V;
+          const double w = double(row[0]);
+          const double ss = double(row[2 + a]) * double(row[2 + b]);
+          if (w2) {
+            sacc += w * w * ss;
+            continue;
+          }
+          double d2 = 0.0;  // sum_c r_c (d2 S_c / S_c)_ab
+          for (int c = 0; c < nc; ++c) {
+            const int rc = rel[c];
+            if (rc == kRelAbsent || rc == kRelZero) continue;
+            const double rv = double(row[2 + nf + c]);
+            const T* l = row + 2 + nf + nc + c * nf;
+            d2 += rv * (rc == kRelProduct ? double(l[a]) * double(l[b])
+                                          : double(row[2 + nf + nc + nc * nf + rc]));
+          }
+          sacc += w * (ss - d2);
+        }
+      }
+      acc[k] += sacc;
+    }
+    __syncthreads();
+  }
+  for (int k = 0; k < kHessSumsPerThread; ++k) {
+    const int j = tid + k * kBlock;
+    if (j < M) A.part[int64_t(j) * gridDim.x + blockIdx.x] = acc[k];
+  }
+}
+
+// Sum j of every tile, in tile order (Neumaier).
+__global__ __launch_bounds__(kBlock) void hess_reduce_kernel(const double* __restrict__ part, int n_tiles,
+                                                             int M, double* __restrict__ out) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= M) return;
+  const double* col = part + int64_t(j) * n_tiles;
+  double s = 0.0, comp = 0.0;
+  for (int t = 0; t < n_tiles; ++t) {
+    const double x = col[t];
+    const double u = s + x;
+    comp += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
+    s = u;
+  }
+  out[j] = s + comp;
+}
+
+size_t hess_lds_bytes(int row_len, int chunk, int precision) {
+  return sizeof(Plan) + sizeof(ConstBlock) + sizeof(HessPlan) + sizeof(double) * 4 * kMaxFac +
+         size_t(row_len) * chunk * (precision == UML_MIXED ? 4 : 8);
+}
+
+void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, double* d_hc,
+                    double* d_out, int precision, hipStream_t s) {
+  hipLaunchKernelGGL(hess_prologue_kernel, dim3(1), dim3(64), 0, s, A.plan, d_theta, d_cb, d_hc);
+  const size_t lds = hess_lds_bytes(A.row_len, A.chunk, precision);
+  if (precision == UML_MIXED)
+    hipLaunchKernelGGL(hess_kernel<float>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
+  else
+    hipLaunchKernelGGL(hess_kernel<double>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
+  hipLaunchKernelGGL(hess_reduce_kernel, dim3((A.n_sums + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     A.part, A.n_tiles, A.n_sums, d_out);
+}
+
+}  // namespace uml

@@ -5,6 +5,7 @@
 
 #include <string>
 
+#include "hess.h"
 #include "kernels.h"
 #include "uml_internal.h"
 
@@ -13,6 +14,9 @@ struct uml_model {
   uml::Plan* d_plan = nullptr;     // device copy
   const uml::Family* family = nullptr;
   int device = 0;
+  uml::HessPlan hplan;
+  uml::HessPlan* d_hplan = nullptr;  // device copy (nullptr: no Hessian, see hess_err)
+  std::string hess_err;
 };
 
 struct uml_data {
@@ -27,8 +31,8 @@ struct uml_data {
   uml::Job* d_job = nullptr;
   double* d_theta = nullptr;        // staging for host theta
   double* d_out = nullptr;          // [1 + nfree]
-  double* d_hess_part = nullptr;    // Hessian tile partials (allocated on first use)
-  int64_t hess_part_elems = 0;
+  void* d_hwork = nullptr;          // Hessian workspace (allocated on first use)
+  int hess_tiles = 0;
   double* h_stage = nullptr;        // pinned host staging
   int64_t bytes_events = 0;
   int64_t bytes_work = 0;

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "hess.h"
 #include "host.h"
 
 namespace uml {
@@ -393,6 +394,83 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
   }
   P.precision = d->precision;
   return UML_OK;
+}
+
+bool build_hess_plan(const Plan& P, HessPlan& H, std::string& err) {
+  std::memset(&H, 0, sizeof(H));
+  int nq = 0;
+  for (int f = 0; f < P.nfac; ++f) {
+    const FactorPlan& F = P.fac[f];
+    H.q_off[f] = nq;
+    nq += F.kind == FK_GAUSS ? 3 : F.kind == FK_EXP ? 1 : F.kind == FK_CHEB ? F.order * (F.order + 1) / 2 : 0;
+  }
+  H.nq = nq;
+  // unit of every parameter in every component: fraction entry k -> 1000 + k,
+  // factor j -> j (local index loc), absent -> -1
+  std::vector<std::vector<int>> unit(P.ncomp, std::vector<int>(P.npar, -1)), loc = unit;
+  for (int c = 0; c < P.ncomp; ++c) {
+    const CompPlan& C = P.comp[c];
+    for (int k = 0; k < C.nfrac; ++k) {
+      if (unit[c][C.frac_par[k]] != -1) {
+        err = "a parameter appears twice in one mixture component";
+        return false;
+      }
+      unit[c][C.frac_par[k]] = 1000 + k;
+    }
+    for (int j = 0; j < C.nfac; ++j) {
+      const FactorPlan& F = P.fac[C.fac[j]];
+      const int np = F.kind == FK_GAUSS ? 2 : F.kind == FK_EXP ? 1 : F.kind == FK_CHEB ? F.order : 8;
+      for (int m = 0; m < np; ++m) {
+        if (unit[c][F.par[m]] != -1) {
+          err = "a parameter appears twice in one mixture component";
+          return false;
+        }
+        unit[c][F.par[m]] = j;
+        loc[c][F.par[m]] = m;
+      }
+    }
+  }
+  int np = 0;
+  for (int a = 0; a < P.nfree; ++a)
+    for (int b = a; b < P.nfree; ++b, ++np) {
+      H.pa[np] = short(a);
+      H.pb[np] = short(b);
+      const int pa = P.free_idx[a], pb = P.free_idx[b];
+      for (int c = 0; c < kMaxComp; ++c) {
+        signed char r = kRelAbsent;
+        if (c < P.ncomp && unit[c][pa] >= 0 && unit[c][pb] >= 0) {
+          const int ua = unit[c][pa], ub = unit[c][pb];
+          if (ua != ub) {
+            r = kRelProduct;
+          } else if (ua >= 1000) {
+            r = kRelZero;
+          } else {
+            const int fi = P.comp[c].fac[ua];
+            const FactorPlan& F = P.fac[fi];
+            int i = loc[c][pa], j = loc[c][pb];
+            if (i > j) std::swap(i, j);
+            if (F.kind == FK_PWAVE) {
+              r = kRelZero;
+            } else {
+              const int k = F.kind == FK_GAUSS ? 2 : F.kind == FK_EXP ? 1 : F.order;
+              const int tri = i * k - i * (i - 1) / 2 + (j - i);
+              r = (signed char)(H.q_off[fi] + tri);
+            }
+          }
+        }
+        H.rel[np * kMaxComp + c] = r;
+      }
+    }
+  H.npairs = np;
+  if (nq > 120) {
+    err = "too many second-derivative entries";
+    return false;
+  }
+  return true;
+}
+
+int hess_row_len(const Plan& P, const HessPlan& H) {
+  return 2 + P.nfree + P.ncomp + P.ncomp * P.nfree + H.nq;
 }
 
 std::string plan_describe(const Plan& P) {
