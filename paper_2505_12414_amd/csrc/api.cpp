@@ -51,6 +51,8 @@ int uml_model_create(const uml_model_desc* desc, uml_model** out) {
     delete m;
     return set_error(UML_E_INVALID, "uml_model_create: internal layout mismatch for " + sig);
   }
+  m->theta0.resize(desc->n_params);
+  for (int k = 0; k < desc->n_params; ++k) m->theta0[k] = desc->params[k].value;
   const bool have_hess = build_hess_plan(m->plan, m->hplan, m->hess_err);
   hipError_t e = hipGetDevice(&m->device);
   if (e == hipSuccess) e = hipMalloc(&m->d_plan, sizeof(Plan));

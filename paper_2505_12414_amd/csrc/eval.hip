@@ -510,6 +510,165 @@ __device__ __forceinline__ double to_sgpr(double v) {
 }
 
 // ---------------------------------------------------------------------------
+// device-resident BFGS (one step per evaluation)
+// ---------------------------------------------------------------------------
+
+// One step of the quasi-Newton minimisation (the Broyden-Fletcher-Goldfarb-
+// Shanno variant of the variable-metric method Migrad uses, Sec. 2.1) for the
+// fit whose trial point this workgroup just evaluated (fs->out).  FP64; thread
+// i < n owns row i of the metric V.  Line search: backtracking from a unit
+// step with the Armijo condition; a rise of the NLL below the rounding level
+// tol_f_rel |f| is accepted when the slope along p has not turned up (strong
+// Wolfe curvature), so mixed-precision rounding cannot stall the search.
+// Stops when EDM = 0.5 g^T V g < edm_tol.  Writes the next trial point and
+// its constants (the next launch's cache) unless the fit is finished.
+__device__ __noinline__ void bfgs_step(const Plan& P, FitState* fs, ConstBlock* cst) {
+  __shared__ double sv[4][UML_MAX_PARAMS];  // s, y, V y, new gradient
+  __shared__ double sc[4];
+  __shared__ int act, fin;
+  const int tid = threadIdx.x, nf = P.nfree;
+  if (tid == 0) {
+    const double ft = fs->out[0];
+    fs->n_eval++;
+    int a;
+    if (fs->phase == 0) {
+      a = isfinite(ft) ? 0 : 3;
+    } else {
+      const double f = fs->f, gp = fs->gp, al = fs->alpha;
+      bool ok = isfinite(ft) && ft <= f + 1e-4 * al * gp + fs->tol_f_rel * fabs(f);
+      if (ok && ft > f + 1e-4 * al * gp) {  // accepted on the rounding tolerance only
+        double gtp = 0.0;
+        for (int k = 0; k < nf; ++k) gtp += fs->out[1 + k] * fs->p[k];
+        ok = fabs(gtp) <= 0.9 * fabs(gp);
+      }
+      a = ok ? 1 : 2;
+    }
+    act = a;
+    fin = 0;
+  }
+  __syncthreads();
+  const int a = act;
+  if (a == 3) {  // the start point has P <= 0 somewhere
+    if (tid == 0) {
+      fs->status = UML_FIT_PDF_NONPOSITIVE;
+      fs->done = 1;
+    }
+    return;
+  }
+  if (a == 1) {  // accept x + alpha p, update the metric
+    if (tid < nf) {
+      const double sk = fs->alpha * fs->p[tid];
+      sv[0][tid] = sk;
+      sv[1][tid] = fs->out[1 + tid] - fs->g[tid];
+      sv[3][tid] = fs->out[1 + tid];
+    }
+    __syncthreads();
+    if (tid < nf) {
+      double vy = 0.0;
+      for (int j = 0; j < nf; ++j) vy += fs->V[tid * UML_MAX_PARAMS + j] * sv[1][j];
+      sv[2][tid] = vy;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double sy = 0.0, yvy = 0.0;
+      for (int k = 0; k < nf; ++k) {
+        sy += sv[0][k] * sv[1][k];
+        yvy += sv[1][k] * sv[2][k];
+      }
+      sc[0] = sy;
+      sc[1] = yvy;
+    }
+    __syncthreads();
+    const double sy = sc[0], yvy = sc[1];
+    if (tid < nf) {
+      if (sy > 0.0 && isfinite(sy) && isfinite(yvy)) {
+        const double c1 = (sy + yvy) / (sy * sy);
+        for (int j = 0; j < nf; ++j)
+          fs->V[tid * UML_MAX_PARAMS + j] +=
+              c1 * sv[0][tid] * sv[0][j] - (sv[2][tid] * sv[0][j] + sv[0][tid] * sv[2][j]) / sy;
+      }
+      fs->x[tid] += sv[0][tid];
+      fs->g[tid] = sv[3][tid];
+    }
+    if (tid == 0) {
+      fs->f = fs->out[0];
+      fs->n_iter++;
+      fs->n_ls = 0;
+    }
+    __syncthreads();
+  } else if (a == 0) {  // the start point
+    if (tid < nf) {
+      fs->x[tid] = fs->theta[P.free_idx[tid]];
+      fs->g[tid] = fs->out[1 + tid];
+    }
+    if (tid == 0) fs->f = fs->out[0];
+    __syncthreads();
+  }
+  if (a == 0 || a == 1) {  // new direction p = -V g
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (tid < nf) {
+        double pk = 0.0;
+        for (int j = 0; j < nf; ++j) pk -= fs->V[tid * UML_MAX_PARAMS + j] * fs->g[j];
+        fs->p[tid] = pk;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double gp = 0.0;
+        for (int k = 0; k < nf; ++k) gp += fs->g[k] * fs->p[k];
+        sc[2] = gp;
+      }
+      __syncthreads();
+      if (sc[2] < 0.0 || nf == 0) break;
+      if (tid < nf)  // the metric lost positivity: restart from the start metric
+        for (int j = 0; j < nf; ++j) fs->V[tid * UML_MAX_PARAMS + j] = fs->V0[tid * UML_MAX_PARAMS + j];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double gp = sc[2];
+      fs->gp = gp;
+      fs->edm = -0.5 * gp;
+      fs->alpha = 1.0;
+      fs->phase = 1;
+      if (nf == 0 || fs->edm < fs->edm_tol) {
+        fs->status = UML_FIT_CONVERGED;
+        fin = 1;
+      } else if (!(gp < 0.0)) {
+        fs->status = UML_FIT_HESSIAN_NOT_PD;
+        fin = 1;
+      } else if (fs->n_iter >= fs->max_iter) {
+        fs->status = UML_FIT_MAX_ITER;
+        fin = 1;
+      }
+    }
+  } else if (tid == 0) {  // a == 2: shorten the step
+    const double ft = fs->out[0], f = fs->f, gp = fs->gp, al = fs->alpha;
+    double an;
+    if (!isfinite(ft)) {
+      an = 0.25 * al;
+    } else {
+      const double q = -gp * al * al / (2.0 * (ft - f - gp * al));
+      an = fmin(fmax(q, 0.1 * al), 0.5 * al);
+    }
+    fs->alpha = an;
+    fs->n_ls++;
+    if (fs->n_ls > 60 || an < 1e-12) {
+      fs->status = fs->edm < 100.0 * fs->edm_tol ? UML_FIT_CONVERGED : UML_FIT_LINESEARCH_FAIL;
+      fin = 1;
+    }
+  }
+  __syncthreads();
+  if (fin) {
+    if (tid < nf) fs->theta[P.free_idx[tid]] = fs->x[tid];
+    __syncthreads();
+    if (tid == 0) fs->done = 1;
+    return;
+  }
+  if (tid < nf) fs->theta[P.free_idx[tid]] = fs->x[tid] + fs->alpha * fs->p[tid];
+  __syncthreads();
+  if (tid == 0) compute_constants(P, fs->theta, cst);  // the next launch's cache
+}
+
+// ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
 
@@ -535,6 +694,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
     if (jid < 0) return;
   }
   const Job J = tmap ? jobs[jid] : j0;
+  if (J.fit && J.fit->done) return;  // a finished fit: its tiles do nothing
   __shared__ __align__(16) ConstBlock s_cb;
   const double* __restrict__ th = (theta_override && !tmap) ? theta_override : J.theta;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -660,6 +820,10 @@ top_level:
   if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
   column_sums<K>(gpart, kGroups, ng, 1, red2, tot);
   epilogue(*s_plan, cb, tot, (out_override && !tmap) ? out_override : J.out);
+  if (J.fit) {
+    __syncthreads();
+    bfgs_step(*s_plan, J.fit, J.cst);
+  }
 }
 
 template <class S>

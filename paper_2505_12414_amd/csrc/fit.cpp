@@ -94,6 +94,244 @@ int unpack_hessian(const uml_model* m, const std::vector<double>& h, double* nll
   return UML_OK;
 }
 
+// Inverse of a symmetric positive-definite n x n matrix (row-major) by
+// Cholesky factorisation, in FP64.  Returns false if A is not PD.
+bool chol_inverse(int n, const double* A, double* Ai) {
+  std::vector<double> L(size_t(n) * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0.0) || !std::isfinite(s)) return false;
+    L[j * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / L[j * n + j];
+    }
+  }
+  std::vector<double> y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
+      y[i] = t / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < n; ++k) t -= L[k * n + i] * Ai[k * n + c];
+      Ai[i * n + c] = t / L[i * n + i];
+    }
+  }
+  return true;
+}
+
+// The start metric: the inverse of the analytic Hessian at the start point
+// (its diagonal inverse if the Hessian is not positive definite there).
+static int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V0,
+                        double* nll0, const char* fn) {
+  const int nf = m->plan.nfree;
+  std::vector<double> h;
+  int rc = hessian_host(m, d, theta, nullptr, h, fn);
+  if (rc != UML_OK) return rc;
+  std::vector<double> H(size_t(nf) * nf);
+  rc = unpack_hessian(m, h, nll0, nullptr, H.data(), nullptr, fn);
+  if (rc != UML_OK) return rc;
+  std::vector<double> Vi(size_t(nf) * nf);
+  for (int i = 0; i < UML_MAX_PARAMS * UML_MAX_PARAMS; ++i) V0[i] = 0.0;
+  if (chol_inverse(nf, H.data(), Vi.data())) {
+    for (int i = 0; i < nf; ++i)
+      for (int j = 0; j < nf; ++j) V0[i * UML_MAX_PARAMS + j] = Vi[i * nf + j];
+  } else {
+    for (int i = 0; i < nf; ++i) {
+      const double hii = std::fabs(H[i * nf + i]);
+      V0[i * UML_MAX_PARAMS + i] = hii > 0.0 ? 1.0 / hii : 1.0;
+    }
+  }
+  return UML_OK;
+}
+
+// Final HESSE-like step at the fitted point (and optional Newton polish):
+// covariance = inverse Hessian, errors, EDM with the exact Hessian.
+static int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta, int polish,
+                      int want_cov, uml_fit_result* r, const char* fn) {
+  const Plan& P = m->plan;
+  const int nf = P.nfree;
+  std::vector<double> h, g(nf), H(size_t(nf) * nf), C(size_t(nf) * nf);
+  double nll = 0.0;
+  for (int it = 0; it <= polish; ++it) {
+    int rc = hessian_host(m, d, theta.data(), nullptr, h, fn);
+    if (rc != UML_OK) return rc;
+    rc = unpack_hessian(m, h, &nll, g.data(), H.data(), nullptr, fn);
+    if (rc != UML_OK) {
+      r->status = UML_FIT_PDF_NONPOSITIVE;
+      return UML_OK;
+    }
+    const bool pd = chol_inverse(nf, H.data(), C.data());
+    if (!pd) {
+      if (r->status == UML_FIT_CONVERGED) r->status = UML_FIT_HESSIAN_NOT_PD;
+      break;
+    }
+    if (it == polish) break;
+    std::vector<double> t2 = theta;  // Newton step with the analytic Hessian
+    for (int a = 0; a < nf; ++a) {
+      double st = 0.0;
+      for (int b = 0; b < nf; ++b) st -= C[a * nf + b] * g[b];
+      t2[P.free_idx[a]] += st;
+    }
+    theta.swap(t2);
+  }
+  double edm = 0.0;
+  for (int a = 0; a < nf; ++a)
+    for (int b = 0; b < nf; ++b) edm += 0.5 * g[a] * C[a * nf + b] * g[b];
+  for (int k = 0; k < UML_MAX_PARAMS; ++k) {
+    r->params[k] = k < P.npar ? theta[k] : 0.0;
+    r->errors[k] = 0.0;
+  }
+  for (int a = 0; a < nf; ++a) {
+    r->errors[P.free_idx[a]] = std::sqrt(std::max(C[a * nf + a], 0.0));
+    for (int b = 0; b < nf; ++b) r->cov[a * nf + b] = want_cov ? C[a * nf + b] : 0.0;
+  }
+  r->nll = nll;
+  r->edm = edm;
+  return UML_OK;
+}
+
+int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const double* starts,
+                   const uml_fit_options* opts, uml_fit_result* out, const char* fn) {
+  uml_fit_options o;
+  uml_fit_options_default(&o);
+  if (opts) o = *opts;
+  if (n == 0) return UML_OK;
+  const Plan& P = m->plan;
+  for (int i = 0; i < n; ++i) {
+    if (!ds[i] || ds[i]->model != m)
+      return set_error(UML_E_INVALID, std::string(fn) + ": data " + std::to_string(i) +
+                                          " is null or belongs to another model");
+    for (int j = 0; j < i; ++j)
+      if (ds[j] == ds[i])
+        return set_error(UML_E_INVALID, std::string(fn) + ": the same data handle appears twice");
+  }
+  std::vector<FitState> fs(n);
+  std::vector<int> live;
+  for (int i = 0; i < n; ++i) {
+    FitState& F = fs[i];
+    std::memset(&F, 0, sizeof(F));
+    std::memset(&out[i], 0, sizeof(uml_fit_result));
+    out[i].n_free = P.nfree;
+    const double* st = starts + size_t(i) * P.npar;
+    for (int k = 0; k < P.npar; ++k) F.theta[k] = st[k];
+    double nll0 = 0.0;
+    int rc = start_metric(m, const_cast<uml_data*>(ds[i]), st, F.V0, &nll0, fn);
+    if (rc == UML_E_PDF_NONPOSITIVE) {
+      F.done = 1;
+      F.status = UML_FIT_PDF_NONPOSITIVE;
+      continue;
+    }
+    if (rc != UML_OK) return rc;
+    std::memcpy(F.V, F.V0, sizeof(F.V));
+    F.phase = 0;
+    F.alpha = 1.0;
+    F.edm = INFINITY;
+    F.edm_tol = o.edm_tol;
+    F.max_iter = o.max_iter;
+    // NLL rounding: FP64 sums to ~1e-15 relative.  In mixed mode each
+    // parameter-only constant is rounded to FP32 once per point, which moves
+    // ln P of every event of a component together by up to ~2^-24 |log2 K|:
+    // the NLL steps by a few 1e-8 of itself between nearby points.
+    F.tol_f_rel = P.precision == UML_MIXED ? 2e-7 : 1e-14;
+    live.push_back(i);
+  }
+  // device state: fit states | jobs | tile map
+  int total_tiles = 0;
+  for (int i : live) total_tiles += ds[i]->n_tiles;
+  const size_t o_fs = 0, o_job = (sizeof(FitState) * n + 255) / 256 * 256;
+  const size_t o_map = o_job + (sizeof(Job) * n + 255) / 256 * 256;
+  const size_t bytes = o_map + sizeof(int2) * std::max(total_tiles, 1);
+  void* dmem = nullptr;
+  hipError_t e = hipMalloc(&dmem, bytes);
+  if (e != hipSuccess) return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
+  struct Free {
+    void* p;
+    ~Free() { if (p) (void)hipFree(p); }
+  } guard{dmem};
+  char* base = static_cast<char*>(dmem);
+  FitState* d_fs = reinterpret_cast<FitState*>(base + o_fs);
+  Job* d_jobs = reinterpret_cast<Job*>(base + o_job);
+  int2* d_map = reinterpret_cast<int2*>(base + o_map);
+  std::vector<Job> jobs(n);
+  for (int i = 0; i < n; ++i) {
+    jobs[i] = ds[i]->job;
+    jobs[i].fit = d_fs + i;
+    jobs[i].theta = d_fs[i].theta;
+    jobs[i].out = d_fs[i].out;
+  }
+  hipStream_t s = nullptr;
+  auto build_map = [&](std::vector<int2>& map) {
+    map.clear();
+    for (int i : live)
+      for (int t = 0; t < ds[i]->n_tiles; ++t) map.push_back(make_int2(i, t));
+  };
+  std::vector<int2> map;
+  build_map(map);
+  UML_HIP_CHECK(hipMemcpyAsync(d_fs, fs.data(), sizeof(FitState) * n, hipMemcpyHostToDevice, s));
+  UML_HIP_CHECK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
+  if (!map.empty())
+    UML_HIP_CHECK(hipMemcpyAsync(d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice, s));
+  std::vector<int> done(n, 0);
+  int launches = 0, since_poll = 0, poll_every = 2;
+  const int max_launches = std::max(1, o.max_iter) * 64 + 64;
+  while (!map.empty() && launches < max_launches) {
+    LaunchArgs a{};
+    a.job0 = jobs[0];
+    a.jobs = d_jobs;
+    a.tmap = d_map;
+    a.grid = int(map.size());
+    a.precision = P.precision;
+    a.stream = s;
+    m->family->eval(a);
+    UML_HIP_CHECK(hipGetLastError());
+    ++launches;
+    if (++since_poll < poll_every) continue;
+    since_poll = 0;
+    poll_every = std::min(poll_every * 2, 16);
+    UML_HIP_CHECK(hipMemcpy2DAsync(done.data(), sizeof(int), &d_fs[0].done, sizeof(FitState),
+                                   sizeof(int), n, hipMemcpyDeviceToHost, s));
+    UML_HIP_CHECK(hipStreamSynchronize(s));
+    std::vector<int> still;
+    for (int i : live)
+      if (!done[i]) still.push_back(i);
+    if (still.size() != live.size()) {
+      live.swap(still);
+      build_map(map);
+      if (!map.empty())
+        UML_HIP_CHECK(hipMemcpyAsync(d_map, map.data(), sizeof(int2) * map.size(),
+                                     hipMemcpyHostToDevice, s));
+      poll_every = 2;
+    }
+  }
+  UML_HIP_CHECK(hipMemcpyAsync(fs.data(), d_fs, sizeof(FitState) * n, hipMemcpyDeviceToHost, s));
+  UML_HIP_CHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < n; ++i) {
+    FitState& F = fs[i];
+    uml_fit_result& r = out[i];
+    r.n_free = P.nfree;
+    r.n_iter = F.n_iter;
+    r.n_eval = F.n_eval;
+    r.status = F.done ? F.status : UML_FIT_MAX_ITER;
+    std::vector<double> theta(F.theta, F.theta + P.npar);
+    if (!F.done)
+      for (int a = 0; a < P.nfree; ++a) theta[P.free_idx[a]] = F.x[a];
+    if (r.status == UML_FIT_PDF_NONPOSITIVE) {
+      for (int k = 0; k < P.npar; ++k) r.params[k] = theta[k];
+      r.nll = INFINITY;
+      continue;
+    }
+    int rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o.polish, o.want_cov, &r, fn);
+    if (rc != UML_OK) return rc;
+  }
+  return UML_OK;
+}
+
 }  // namespace uml
 
 extern "C" {
@@ -115,14 +353,20 @@ int uml_eval_hessian(const uml_model* m, const uml_data* d, const double* theta_
   return unpack_hessian(m, h, nll, grad_free, hess_free, w2_free, "uml_eval_hessian");
 }
 
-int uml_fit(const uml_model*, const uml_data*, const double*, const uml_fit_options*,
-            uml_fit_result*) {
-  return set_error(UML_E_UNSUPPORTED, "uml_fit: not built yet");
+int uml_fit(const uml_model* m, const uml_data* d, const double* start_all,
+            const uml_fit_options* opts, uml_fit_result* out) {
+  const uml_data* ds[1] = {d};
+  if (!m) return set_error(UML_E_INVALID, "uml_fit: null model");
+  std::vector<double> st(m->plan.npar);
+  for (int k = 0; k < m->plan.npar; ++k) st[k] = start_all ? start_all[k] : m->theta0[k];
+  return fit_batch_impl(m, ds, 1, st.data(), opts, out, "uml_fit");
 }
 
-int uml_fit_batch(const uml_model*, const uml_data* const*, int32_t, const double*,
-                  const uml_fit_options*, uml_fit_result*) {
-  return set_error(UML_E_UNSUPPORTED, "uml_fit_batch: not built yet");
+int uml_fit_batch(const uml_model* m, const uml_data* const* ds, int32_t n_fits, const double* starts,
+                  const uml_fit_options* opts, uml_fit_result* out) {
+  if (!m || !ds || n_fits < 0 || (n_fits > 0 && (!starts || !out)))
+    return set_error(UML_E_INVALID, "uml_fit_batch: bad argument");
+  return fit_batch_impl(m, ds, n_fits, starts, opts, out, "uml_fit_batch");
 }
 
 }  // extern "C"

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "hess.h"
 #include "kernels.h"
@@ -11,6 +12,7 @@
 
 struct uml_model {
   uml::Plan plan;
+  std::vector<double> theta0;      // parameter values of the description
   uml::Plan* d_plan = nullptr;     // device copy
   const uml::Family* family = nullptr;
   int device = 0;
@@ -46,6 +48,14 @@ std::string plan_describe(const Plan& P);
 
 // thread-local error message
 int set_error(int code, const std::string& msg);
+
+int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
+                 std::vector<double>& out, const char* fn);
+int unpack_hessian(const uml_model* m, const std::vector<double>& h, double* nll, double* grad,
+                   double* hess, double* w2, const char* fn);
+bool chol_inverse(int n, const double* A, double* Ai);
+int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const double* starts,
+                   const uml_fit_options* opts, uml_fit_result* out, const char* fn);
 
 #define UML_HIP_CHECK(expr)                                                         \
   do {                                                                              \

@@ -125,23 +125,29 @@ struct ConstBlock {
 };
 static_assert(sizeof(ConstBlock) % 16 == 0, "ConstBlock is copied in 16-byte units");
 
-// Device-resident state of one BFGS fit (one per job in fit mode).
+// Device-resident state of one BFGS fit (one per job in fit mode).  Every
+// launch evaluates the NLL and gradient at theta; the workgroup that
+// completes the evaluation takes the BFGS step and writes the next theta.
 struct FitState {
-  double x[UML_MAX_PARAMS];       // accepted point (free parameters)
-  double g[UML_MAX_PARAMS];       // gradient there
-  double f;                       // NLL there
-  double V[UML_MAX_PARAMS * UML_MAX_PARAMS];  // inverse-Hessian estimate
-  double p[UML_MAX_PARAMS];       // search direction
-  double gp;                      // g . p
-  double alpha;                   // current trial step
-  double edm;
-  double theta[UML_MAX_PARAMS];   // full parameter vector of the trial point
-  int phase;                      // 0: first evaluation, 1: line search
-  int n_iter, n_eval, n_ls;
-  int done;                       // 0 running, 1 finished
-  int status;                     // UML_FIT_*
+  double theta[UML_MAX_PARAMS];       // point evaluated by the next launch (all parameters)
+  double out[1 + UML_MAX_PARAMS];     // NLL and free gradient at theta (epilogue output)
+  double x[UML_MAX_PARAMS];           // accepted point (free parameters)
+  double g[UML_MAX_PARAMS];           // gradient at x
+  double p[UML_MAX_PARAMS];           // search direction
+  double V[UML_MAX_PARAMS * UML_MAX_PARAMS];   // inverse-Hessian estimate
+  double V0[UML_MAX_PARAMS * UML_MAX_PARAMS];  // the start metric (restart value)
+  double f;          // NLL at x
+  double gp;         // g . p
+  double alpha;      // current step length along p
+  double edm;        // 0.5 g^T V g at x
   double edm_tol;
+  double tol_f_rel;  // accepted NLL rise from rounding, relative to |f|
+  int phase;         // 0: evaluating the start point; 1: line search along p
+  int n_iter, n_eval, n_ls;
+  int done;          // 0 running; 1 finished (status set)
+  int status;        // UML_FIT_*
   int max_iter;
+  int pad_;
 };
 
 // One dataset's share of a launch.
