@@ -20,6 +20,111 @@ int set_error(int code, const std::string& msg) {
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+int convert_events(const Plan& P, int64_t n, const void* const* cols, int32_t dtype, const void* w,
+                   std::vector<char>& host, const char* fn) {
+  if (n < 0) return set_error(UML_E_INVALID, std::string(fn) + ": negative event count");
+  if (dtype != UML_F32 && dtype != UML_F64)
+    return set_error(UML_E_INVALID, std::string(fn) + ": dtype must be UML_F32 or UML_F64");
+  if (n > 0 && !cols) return set_error(UML_E_INVALID, std::string(fn) + ": cols is NULL");
+  if (n > 0)
+    for (int ud = 0; ud < P.ndim; ++ud)
+      if (!cols[ud]) return set_error(UML_E_INVALID, std::string(fn) + ": column pointer is NULL");
+  const bool mixed = P.precision == UML_MIXED;
+  const size_t esz = mixed ? 4 : 8;
+  const int ncols = P.ndim + (w ? 1 : 0);
+  const int64_t stride = align_up(std::max<int64_t>(n, 1), 64);  // elements per column
+  host.assign(size_t(stride) * esz * ncols, 0);
+  for (int kd = 0; kd < ncols; ++kd) {
+    const bool is_w = kd == P.ndim;
+    const int ud = is_w ? -1 : P.user_of_dim[kd];
+    const void* sp = is_w ? w : (n > 0 ? cols[ud] : nullptr);
+    const double lo = is_w ? 0 : P.lo[kd], hi = is_w ? 0 : P.hi[kd];
+    char* dst = host.data() + size_t(kd) * stride * esz;
+    for (int64_t i = 0; i < n; ++i) {
+      double v = dtype == UML_F32 ? double(static_cast<const float*>(sp)[i])
+                                  : static_cast<const double*>(sp)[i];
+      double stored = mixed ? double(float(v)) : v;
+      if (is_w) {
+        if (!std::isfinite(stored))
+          return set_error(UML_E_EVENT_DOMAIN,
+                           std::string(fn) + ": weight " + std::to_string(i) + " is not finite");
+      } else if (!(stored >= lo && stored <= hi)) {
+        return set_error(UML_E_EVENT_DOMAIN,
+                         std::string(fn) + ": event " + std::to_string(i) + " dimension " +
+                             std::to_string(ud) + " value " + std::to_string(v) +
+                             " is outside [" + std::to_string(lo) + ", " + std::to_string(hi) +
+                             "] or NaN" + (mixed ? " (after rounding to FP32)" : ""));
+      }
+      if (mixed)
+        reinterpret_cast<float*>(dst)[i] = float(stored);
+      else
+        reinterpret_cast<double*>(dst)[i] = stored;
+    }
+  }
+  return UML_OK;
+}
+
+DataLayout data_layout(const Plan& P, int64_t n, bool weighted) {
+  DataLayout L{};
+  const size_t esz = P.precision == UML_MIXED ? 4 : 8;
+  L.stride = align_up(std::max<int64_t>(n, 1), 64);
+  L.bytes_events = size_t(L.stride) * esz * (P.ndim + (weighted ? 1 : 0));
+  L.E = events_per_thread(n, P.precision);
+  const int64_t tsize = int64_t(L.E) * kBlock;
+  L.n_tiles = int(std::max<int64_t>(1, (n + tsize - 1) / tsize));
+  // work area: job | constants | theta | out | counters | partials
+  L.o_job = 0;
+  L.o_cst = align_up(L.o_job + sizeof(Job), 256);
+  L.o_theta = align_up(L.o_cst + sizeof(ConstBlock), 256);
+  L.o_out = align_up(L.o_theta + sizeof(double) * UML_MAX_PARAMS, 256);
+  L.o_cnt = align_up(L.o_out + sizeof(double) * (1 + UML_MAX_PARAMS), 256);
+  L.o_part = align_up(L.o_cnt + sizeof(unsigned) * kCounterWords, 256);
+  L.bytes_work = L.o_part + sizeof(double) * P.K * (L.n_tiles + kGroups);
+  return L;
+}
+
+void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const DataLayout& L,
+               void* d_events, void* d_work) {
+  const Plan& P = m->plan;
+  const size_t esz = P.precision == UML_MIXED ? 4 : 8;
+  d->model = m;
+  d->n = n;
+  d->weighted = weighted ? 1 : 0;
+  d->E = L.E;
+  d->n_tiles = L.n_tiles;
+  d->bytes_events = int64_t(L.bytes_events);
+  d->bytes_work = int64_t(L.bytes_work);
+  d->d_events = d_events;
+  d->d_work = d_work;
+  char* wbase = static_cast<char*>(d_work);
+  d->d_job = reinterpret_cast<Job*>(wbase + L.o_job);
+  d->d_theta = reinterpret_cast<double*>(wbase + L.o_theta);
+  d->d_out = reinterpret_cast<double*>(wbase + L.o_out);
+  Job& J = d->job;
+  std::memset(&J, 0, sizeof(J));
+  for (int kd = 0; kd < P.ndim; ++kd)
+    J.col[kd] = static_cast<char*>(d_events) + size_t(kd) * L.stride * esz;
+  J.w = weighted ? static_cast<char*>(d_events) + size_t(P.ndim) * L.stride * esz : nullptr;
+  J.n = n;
+  J.n_tiles = L.n_tiles;
+  J.events_per_thread = L.E;
+  J.cst = reinterpret_cast<ConstBlock*>(wbase + L.o_cst);
+  J.partials = reinterpret_cast<double*>(wbase + L.o_part);
+  J.counter = reinterpret_cast<unsigned int*>(wbase + L.o_cnt);
+  J.out = d->d_out;
+  J.plan = m->d_plan;
+  J.fit = nullptr;
+  J.theta = d->d_theta;
+  J.npar = P.npar;
+}
+
+hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d->d_events, host.data(), host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(d->d_work, 0, L.o_part, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &d->job, sizeof(Job), hipMemcpyHostToDevice, s);
+  return e;
+}
+
 }  // namespace uml
 
 using namespace uml;
@@ -92,92 +197,37 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
   if (!out) return set_error(UML_E_INVALID, "uml_data_create: out is NULL");
   *out = nullptr;
   if (!m) return set_error(UML_E_INVALID, "uml_data_create: model is NULL");
-  if (n < 0) return set_error(UML_E_INVALID, "uml_data_create: negative event count");
-  if (dtype != UML_F32 && dtype != UML_F64)
-    return set_error(UML_E_INVALID, "uml_data_create: dtype must be UML_F32 or UML_F64");
   const Plan& P = m->plan;
-  if (n > 0 && !cols) return set_error(UML_E_INVALID, "uml_data_create: cols is NULL");
-  if (n > 0)
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t ssz = dtype == UML_F32 ? 4 : 8;  // source element
+  if (n > 0 && cols)
     for (int ud = 0; ud < P.ndim; ++ud)
       if (!cols[ud]) return set_error(UML_E_INVALID, "uml_data_create: column pointer is NULL");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool mixed = P.precision == UML_MIXED;
-  const size_t esz = mixed ? 4 : 8;     // storage element
-  const size_t ssz = dtype == UML_F32 ? 4 : 8;  // source element
-
-  // gather the source on the host (device sources are copied back first)
+  // device sources are copied back to the host first
   std::vector<char> hsrc;
-  std::vector<const void*> src(P.ndim + 1, nullptr);
-  if (n > 0) {
-    if (flags & UML_DATA_DEVICE_SRC) {
-      hsrc.resize(size_t(n) * ssz * (P.ndim + (w ? 1 : 0)));
-      for (int ud = 0; ud < P.ndim; ++ud) {
-        UML_HIP_CHECK(hipMemcpy(hsrc.data() + size_t(ud) * n * ssz, cols[ud], n * ssz,
-                                hipMemcpyDeviceToHost));
-        src[ud] = hsrc.data() + size_t(ud) * n * ssz;
-      }
-      if (w) {
-        UML_HIP_CHECK(hipMemcpy(hsrc.data() + size_t(P.ndim) * n * ssz, w, n * ssz,
-                                hipMemcpyDeviceToHost));
-        src[P.ndim] = hsrc.data() + size_t(P.ndim) * n * ssz;
-      }
-    } else {
-      for (int ud = 0; ud < P.ndim; ++ud) src[ud] = cols[ud];
-      src[P.ndim] = w;
+  std::vector<const void*> src(P.ndim, nullptr);
+  const void* wsrc = w;
+  if (n > 0 && cols && (flags & UML_DATA_DEVICE_SRC) && (dtype == UML_F32 || dtype == UML_F64)) {
+    hsrc.resize(size_t(n) * ssz * (P.ndim + (w ? 1 : 0)));
+    for (int ud = 0; ud < P.ndim; ++ud) {
+      UML_HIP_CHECK(hipMemcpy(hsrc.data() + size_t(ud) * n * ssz, cols[ud], n * ssz,
+                              hipMemcpyDeviceToHost));
+      src[ud] = hsrc.data() + size_t(ud) * n * ssz;
     }
-  }
-
-  // convert into kernel-dimension order and storage type, validating ranges
-  const int ncols = P.ndim + (w ? 1 : 0);
-  const int64_t stride = align_up(std::max<int64_t>(n, 1), 64);  // elements per column
-  std::vector<char> host(size_t(stride) * esz * ncols, 0);
-  for (int kd = 0; kd < ncols; ++kd) {
-    const bool is_w = kd == P.ndim;
-    const int ud = is_w ? -1 : P.user_of_dim[kd];
-    const void* sp = is_w ? src[P.ndim] : src[ud];
-    const double lo = is_w ? 0 : P.lo[kd], hi = is_w ? 0 : P.hi[kd];
-    char* dst = host.data() + size_t(kd) * stride * esz;
-    for (int64_t i = 0; i < n; ++i) {
-      double v = dtype == UML_F32 ? double(static_cast<const float*>(sp)[i])
-                                  : static_cast<const double*>(sp)[i];
-      double stored = mixed ? double(float(v)) : v;
-      if (is_w) {
-        if (!std::isfinite(stored))
-          return set_error(UML_E_EVENT_DOMAIN, "uml_data_create: weight " + std::to_string(i) +
-                                                   " is not finite");
-      } else if (!(stored >= lo && stored <= hi)) {
-        return set_error(UML_E_EVENT_DOMAIN,
-                         "uml_data_create: event " + std::to_string(i) + " dimension " +
-                             std::to_string(ud) + " value " + std::to_string(v) +
-                             " is outside [" + std::to_string(lo) + ", " + std::to_string(hi) +
-                             "] or NaN" + (mixed ? " (after rounding to FP32)" : ""));
-      }
-      if (mixed)
-        reinterpret_cast<float*>(dst)[i] = float(stored);
-      else
-        reinterpret_cast<double*>(dst)[i] = stored;
+    if (w) {
+      UML_HIP_CHECK(hipMemcpy(hsrc.data() + size_t(P.ndim) * n * ssz, w, n * ssz,
+                              hipMemcpyDeviceToHost));
+      wsrc = hsrc.data() + size_t(P.ndim) * n * ssz;
     }
+  } else if (n > 0 && cols) {
+    for (int ud = 0; ud < P.ndim; ++ud) src[ud] = cols[ud];
   }
-
+  std::vector<char> host;
+  int rc = convert_events(P, n, n > 0 ? src.data() : nullptr, dtype, wsrc, host, "uml_data_create");
+  if (rc != UML_OK) return rc;
+  const DataLayout L = data_layout(P, n, w != nullptr);
   uml_data* d = new (std::nothrow) uml_data();
   if (!d) return set_error(UML_E_NOMEM, "uml_data_create: out of host memory");
-  d->model = m;
-  d->n = n;
-  d->weighted = w ? 1 : 0;
-  d->E = events_per_thread(n, P.precision);
-  const int64_t tsize = int64_t(d->E) * kBlock;
-  d->n_tiles = int(std::max<int64_t>(1, (n + tsize - 1) / tsize));
-  d->bytes_events = int64_t(host.size());
-
-  // work area: job | constants | theta | out | counter | partials
-  const int64_t o_job = 0;
-  const int64_t o_cst = align_up(o_job + sizeof(Job), 256);
-  const int64_t o_theta = align_up(o_cst + sizeof(ConstBlock), 256);
-  const int64_t o_out = align_up(o_theta + sizeof(double) * UML_MAX_PARAMS, 256);
-  const int64_t o_cnt = align_up(o_out + sizeof(double) * (1 + UML_MAX_PARAMS), 256);
-  const int64_t o_part = align_up(o_cnt + sizeof(unsigned) * kCounterWords, 256);
-  d->bytes_work = o_part + int64_t(sizeof(double)) * P.K * (d->n_tiles + kGroups);
-
   auto fail = [&](hipError_t e, const char* what) {
     if (d->d_events) (void)hipFree(d->d_events);
     if (d->d_work) (void)hipFree(d->d_work);
@@ -186,48 +236,33 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
     return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
                      std::string("uml_data_create: ") + what + ": " + hipGetErrorString(e));
   };
-  hipError_t e = hipMalloc(&d->d_events, host.size());
+  void *dev_ev = nullptr, *dev_work = nullptr;
+  hipError_t e = hipMalloc(&dev_ev, L.bytes_events);
   if (e != hipSuccess) return fail(e, "event buffer");
-  e = hipMalloc(&d->d_work, d->bytes_work);
+  d->d_events = dev_ev;
+  e = hipMalloc(&dev_work, L.bytes_work);
   if (e != hipSuccess) return fail(e, "work buffer");
+  d->d_work = dev_work;
   e = hipHostMalloc(reinterpret_cast<void**>(&d->h_stage), sizeof(double) * 4 * (UML_MAX_PARAMS + 2),
                     hipHostMallocDefault);
   if (e != hipSuccess) return fail(e, "pinned staging");
-  char* wbase = static_cast<char*>(d->d_work);
-  d->d_job = reinterpret_cast<Job*>(wbase + o_job);
-  d->d_theta = reinterpret_cast<double*>(wbase + o_theta);
-  d->d_out = reinterpret_cast<double*>(wbase + o_out);
-  Job& J = d->job;
-  std::memset(&J, 0, sizeof(J));
-  for (int kd = 0; kd < P.ndim; ++kd)
-    J.col[kd] = static_cast<char*>(d->d_events) + size_t(kd) * stride * esz;
-  J.w = w ? static_cast<char*>(d->d_events) + size_t(P.ndim) * stride * esz : nullptr;
-  J.n = n;
-  J.n_tiles = d->n_tiles;
-  J.events_per_thread = d->E;
-  J.cst = reinterpret_cast<ConstBlock*>(wbase + o_cst);
-  J.partials = reinterpret_cast<double*>(wbase + o_part);
-  J.counter = reinterpret_cast<unsigned int*>(wbase + o_cnt);
-  J.out = d->d_out;
-  J.plan = m->d_plan;
-  J.fit = nullptr;
-  J.theta = d->d_theta;
-  J.npar = P.npar;
-  e = hipMemcpyAsync(d->d_events, host.data(), host.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(wbase, 0, o_part, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &J, sizeof(Job), hipMemcpyHostToDevice, s);
+  data_bind(d, m, n, w != nullptr, L, dev_ev, dev_work);
+  e = data_upload(d, L, host, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(e, "upload");
+  d->owns_memory = 1;
   *out = d;
   return UML_OK;
 }
 
 void uml_data_destroy(uml_data* d) {
   if (!d) return;
-  if (d->d_events) (void)hipFree(d->d_events);
-  if (d->d_work) (void)hipFree(d->d_work);
-  if (d->d_hwork) (void)hipFree(d->d_hwork);
-  if (d->h_stage) (void)hipHostFree(d->h_stage);
+  if (d->owns_memory) {
+    if (d->d_events) (void)hipFree(d->d_events);
+    if (d->d_work) (void)hipFree(d->d_work);
+    if (d->d_hwork) (void)hipFree(d->d_hwork);
+    if (d->h_stage) (void)hipHostFree(d->h_stage);
+  }
   delete d;
 }
 

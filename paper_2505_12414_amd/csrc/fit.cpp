@@ -12,6 +12,29 @@ namespace uml {
 
 constexpr int64_t kHessTileEvents = 4096;
 
+// Hessian workspace: constants | hc | out | partials.
+struct HessLayout {
+  size_t o_cb, o_hc, o_out, o_part, bytes;
+  int n_tiles, M;
+};
+static HessLayout hess_layout(const uml_model* m, int64_t n) {
+  HessLayout L{};
+  L.M = 1 + m->plan.nfree + 2 * m->hplan.npairs;
+  L.n_tiles = int(std::max<int64_t>(1, (n + kHessTileEvents - 1) / kHessTileEvents));
+  L.o_cb = 0;
+  L.o_hc = (sizeof(ConstBlock) + 255) / 256 * 256;
+  L.o_out = L.o_hc + 256 * ((sizeof(double) * 4 * kMaxFac + 255) / 256);
+  L.o_part = L.o_out + 256 * ((sizeof(double) * L.M + 255) / 256);
+  L.bytes = L.o_part + sizeof(double) * size_t(L.M) * L.n_tiles;
+  return L;
+}
+
+size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles) {
+  const HessLayout L = hess_layout(m, n);
+  if (n_tiles) *n_tiles = L.n_tiles;
+  return L.bytes;
+}
+
 // Runs the Hessian pass for theta (host) and returns the raw sums
 // [sum w log2 P, sum w s (nfree), H pairs, W2 pairs].
 int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
@@ -23,22 +46,22 @@ int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream
     return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": " + m->hess_err);
   const Plan& P = m->plan;
   const int row = hess_row_len(P, m->hplan);
-  const int M = 1 + P.nfree + 2 * m->hplan.npairs;
-  const int n_tiles = int(std::max<int64_t>(1, (d->n + kHessTileEvents - 1) / kHessTileEvents));
+  const HessLayout HL = hess_layout(m, d->n);
+  const int M = HL.M;
+  const int n_tiles = HL.n_tiles;
   const size_t fixed = hess_lds_bytes(row, 0, P.precision);
   const size_t esz = P.precision == UML_MIXED ? 4 : 8;
   int chunk = 64;
   while (chunk > 1 && fixed + size_t(row) * chunk * esz > 60 * 1024) chunk /= 2;
   if (fixed + size_t(row) * chunk * esz > 64 * 1024)
     return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": model too large for the Hessian pass");
-  // workspace: constants | hc | out | partials
-  const size_t o_cb = 0, o_hc = (sizeof(ConstBlock) + 255) / 256 * 256;
-  const size_t o_out = o_hc + 256 * ((sizeof(double) * 4 * kMaxFac + 255) / 256);
-  const size_t o_part = o_out + 256 * ((sizeof(double) * M + 255) / 256);
+  const size_t o_cb = HL.o_cb, o_hc = HL.o_hc, o_out = HL.o_out, o_part = HL.o_part;
   if (!d->d_hwork || d->hess_tiles != n_tiles) {
+    if (!d->owns_memory)
+      return set_error(UML_E_INVALID, std::string(fn) + ": missing Hessian workspace");
     if (d->d_hwork) (void)hipFree(d->d_hwork);
     d->d_hwork = nullptr;
-    hipError_t e = hipMalloc(&d->d_hwork, o_part + sizeof(double) * size_t(M) * n_tiles);
+    hipError_t e = hipMalloc(&d->d_hwork, HL.bytes);
     if (e != hipSuccess) {
       d->d_hwork = nullptr;
       return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
@@ -127,11 +150,11 @@ bool chol_inverse(int n, const double* A, double* Ai) {
 
 // The start metric: the inverse of the analytic Hessian at the start point
 // (its diagonal inverse if the Hessian is not positive definite there).
-static int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V0,
-                        double* nll0, const char* fn) {
+int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V0, double* nll0,
+                 hipStream_t s, const char* fn) {
   const int nf = m->plan.nfree;
   std::vector<double> h;
-  int rc = hessian_host(m, d, theta, nullptr, h, fn);
+  int rc = hessian_host(m, d, theta, s, h, fn);
   if (rc != UML_OK) return rc;
   std::vector<double> H(size_t(nf) * nf);
   rc = unpack_hessian(m, h, nll0, nullptr, H.data(), nullptr, fn);
@@ -152,14 +175,14 @@ static int start_metric(const uml_model* m, uml_data* d, const double* theta, do
 
 // Final HESSE-like step at the fitted point (and optional Newton polish):
 // covariance = inverse Hessian, errors, EDM with the exact Hessian.
-static int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta, int polish,
-                      int want_cov, uml_fit_result* r, const char* fn) {
+int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta, int polish,
+               int want_cov, uml_fit_result* r, hipStream_t s, const char* fn) {
   const Plan& P = m->plan;
   const int nf = P.nfree;
   std::vector<double> h, g(nf), H(size_t(nf) * nf), C(size_t(nf) * nf);
   double nll = 0.0;
   for (int it = 0; it <= polish; ++it) {
-    int rc = hessian_host(m, d, theta.data(), nullptr, h, fn);
+    int rc = hessian_host(m, d, theta.data(), s, h, fn);
     if (rc != UML_OK) return rc;
     rc = unpack_hessian(m, h, &nll, g.data(), H.data(), nullptr, fn);
     if (rc != UML_OK) {
@@ -196,6 +219,35 @@ static int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& thet
   return UML_OK;
 }
 
+// A fit's device state at its start point (the start metric from the
+// analytic Hessian).  A start with P <= 0 somewhere gives a finished state.
+int init_fit_state(const uml_model* m, uml_data* d, const double* start, const uml_fit_options& o,
+                   FitState& F, hipStream_t s, const char* fn) {
+  const Plan& P = m->plan;
+  std::memset(&F, 0, sizeof(F));
+  for (int k = 0; k < P.npar; ++k) F.theta[k] = start[k];
+  double nll0 = 0.0;
+  int rc = start_metric(m, d, start, F.V0, &nll0, s, fn);
+  if (rc == UML_E_PDF_NONPOSITIVE) {
+    F.done = 1;
+    F.status = UML_FIT_PDF_NONPOSITIVE;
+    return UML_OK;
+  }
+  if (rc != UML_OK) return rc;
+  std::memcpy(F.V, F.V0, sizeof(F.V));
+  F.phase = 0;
+  F.alpha = 1.0;
+  F.edm = INFINITY;
+  F.edm_tol = o.edm_tol;
+  F.max_iter = o.max_iter;
+  // NLL rounding: FP64 sums to ~1e-15 relative.  In mixed mode each
+  // parameter-only constant is rounded to FP32 once per point, which moves
+  // ln P of every event of a component together by up to ~2^-24 |log2 K|:
+  // the NLL steps by a few 1e-8 of itself between nearby points.
+  F.tol_f_rel = P.precision == UML_MIXED ? 2e-7 : 1e-14;
+  return UML_OK;
+}
+
 int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const double* starts,
                    const uml_fit_options* opts, uml_fit_result* out, const char* fn) {
   uml_fit_options o;
@@ -214,32 +266,12 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
   std::vector<FitState> fs(n);
   std::vector<int> live;
   for (int i = 0; i < n; ++i) {
-    FitState& F = fs[i];
-    std::memset(&F, 0, sizeof(F));
     std::memset(&out[i], 0, sizeof(uml_fit_result));
     out[i].n_free = P.nfree;
-    const double* st = starts + size_t(i) * P.npar;
-    for (int k = 0; k < P.npar; ++k) F.theta[k] = st[k];
-    double nll0 = 0.0;
-    int rc = start_metric(m, const_cast<uml_data*>(ds[i]), st, F.V0, &nll0, fn);
-    if (rc == UML_E_PDF_NONPOSITIVE) {
-      F.done = 1;
-      F.status = UML_FIT_PDF_NONPOSITIVE;
-      continue;
-    }
+    int rc = init_fit_state(m, const_cast<uml_data*>(ds[i]), starts + size_t(i) * P.npar, o, fs[i],
+                            nullptr, fn);
     if (rc != UML_OK) return rc;
-    std::memcpy(F.V, F.V0, sizeof(F.V));
-    F.phase = 0;
-    F.alpha = 1.0;
-    F.edm = INFINITY;
-    F.edm_tol = o.edm_tol;
-    F.max_iter = o.max_iter;
-    // NLL rounding: FP64 sums to ~1e-15 relative.  In mixed mode each
-    // parameter-only constant is rounded to FP32 once per point, which moves
-    // ln P of every event of a component together by up to ~2^-24 |log2 K|:
-    // the NLL steps by a few 1e-8 of itself between nearby points.
-    F.tol_f_rel = P.precision == UML_MIXED ? 2e-7 : 1e-14;
-    live.push_back(i);
+    if (!fs[i].done) live.push_back(i);
   }
   // device state: fit states | jobs | tile map
   int total_tiles = 0;
@@ -326,7 +358,7 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
       r.nll = INFINITY;
       continue;
     }
-    int rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o.polish, o.want_cov, &r, fn);
+    int rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o.polish, o.want_cov, &r, nullptr, fn);
     if (rc != UML_OK) return rc;
   }
   return UML_OK;

@@ -38,6 +38,7 @@ struct uml_data {
   double* h_stage = nullptr;        // pinned host staging
   int64_t bytes_events = 0;
   int64_t bytes_work = 0;
+  int owns_memory = 0;              // 0: memory belongs to a server's arena
 };
 
 namespace uml {
@@ -49,11 +50,32 @@ std::string plan_describe(const Plan& P);
 // thread-local error message
 int set_error(int code, const std::string& msg);
 
+// Event storage and work-area layout of a dataset.
+struct DataLayout {
+  int E, n_tiles;
+  int64_t stride;
+  size_t bytes_events, bytes_work;
+  size_t o_job, o_cst, o_theta, o_out, o_cnt, o_part;
+};
+int convert_events(const Plan& P, int64_t n, const void* const* cols, int32_t dtype, const void* w,
+                   std::vector<char>& host, const char* fn);
+DataLayout data_layout(const Plan& P, int64_t n, bool weighted);
+void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const DataLayout& L,
+               void* d_events, void* d_work);
+hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s);
+size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles);
+
 int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
                  std::vector<double>& out, const char* fn);
 int unpack_hessian(const uml_model* m, const std::vector<double>& h, double* nll, double* grad,
                    double* hess, double* w2, const char* fn);
 bool chol_inverse(int n, const double* A, double* Ai);
+int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V0, double* nll0,
+                 hipStream_t s, const char* fn);
+int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta, int polish,
+               int want_cov, uml_fit_result* r, hipStream_t s, const char* fn);
+int init_fit_state(const uml_model* m, uml_data* d, const double* start, const uml_fit_options& o,
+                   FitState& F, hipStream_t s, const char* fn);
 int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const double* starts,
                    const uml_fit_options* opts, uml_fit_result* out, const char* fn);
 

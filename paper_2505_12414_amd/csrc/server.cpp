@@ -1,7 +1,374 @@
-// Serving loop for many pseudo-experiment fits.
+// Serving loop for many pseudo-experiment fits of one model (the coverage
+// studies that motivate fast fitting, Sec. 1; the toy study loop of the
+// benchmark protocol, Sec. 3.1).
+//
+// One worker thread owns the device.  Requests are converted and validated
+// on the submitting thread and queued.  The worker admits them while a slot
+// is free and their event storage and workspaces fit the device arena (the
+// memory budget), starts each fit (start metric from the analytic Hessian),
+// and advances every active fit with one ragged launch per iteration: the
+// event kernel over all active fits' tiles, each fit's last workgroup taking
+// its BFGS step.  Consecutive iterations with an unchanged active set are
+// replayed from a captured HIP graph.  Finished fits are retired between
+// replays (final Hessian for the covariance), freeing their slot and memory
+// for new requests.  A fit's arithmetic does not depend on what else shares
+// the launch, so its result is bitwise the same as a lone uml_fit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
 #include "host.h"
 
+namespace uml {
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over one device allocation (256-byte granules).
+class Arena {
+ public:
+  void init(char* base, size_t cap) {
+    base_ = base;
+    cap_ = cap;
+    free_.clear();
+    if (cap) free_[0] = cap;
+  }
+  bool alloc(size_t size, size_t* off) {
+    size = (size + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < size) continue;
+      *off = it->first;
+      const size_t rest = it->second - size, at = it->first + size;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      used_ += size;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t size) {
+    size = (size + 255) / 256 * 256;
+    used_ -= size;
+    auto it = free_.emplace(off, size).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  char* at(size_t off) const { return base_ + off; }
+  size_t used() const { return used_; }
+  size_t cap() const { return cap_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  int64_t n = 0;
+  bool weighted = false;
+  std::vector<char> host;     // converted event storage (kernel order)
+  std::vector<double> start;  // all parameters
+  size_t bytes = 0;           // arena footprint
+  double t_submit = 0.0;
+};
+
+struct Slot {
+  bool used = false;
+  Request req;
+  uml_data data;
+  size_t off = 0;
+  DataLayout layout{};
+  size_t o_work = 0, o_hess = 0;
+};
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+}  // namespace uml
+
 using namespace uml;
+
+struct uml_server {
+  const uml_model* m = nullptr;
+  uml_server_options opt{};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_result;
+  std::deque<Request> pending;
+  std::deque<uml_fit_result> results;
+  uint64_t next_ticket = 1;
+  int64_t submitted = 0, admitted = 0, finished = 0, iterations = 0, resident = 0;
+  int active = 0;
+  bool stop = false;
+  int worker_error = 0;
+  std::string worker_msg;
+  std::thread worker;
+  // device state
+  hipStream_t stream = nullptr;
+  void* arena_mem = nullptr;
+  void* state_mem = nullptr;
+  Arena arena;
+  FitState* d_fs = nullptr;
+  Job* d_jobs = nullptr;
+  int2* d_map = nullptr;
+  int map_cap = 0;
+  double* h_stage = nullptr;
+  std::vector<Slot> slots;
+  std::vector<Job> jobs;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_grid = -1;
+};
+
+namespace uml {
+namespace {
+
+constexpr int kItersPerReplay = 4;
+
+size_t request_bytes(const uml_model* m, int64_t n, bool weighted) {
+  const DataLayout L = data_layout(m->plan, n, weighted);
+  int ht = 0;
+  return round256(L.bytes_events) + round256(L.bytes_work) + round256(hess_work_bytes(m, n, &ht));
+}
+
+int fail_worker(uml_server* S, int code, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->worker_error = code;
+  S->worker_msg = msg;
+  S->stop = true;
+  S->cv_result.notify_all();
+  return code;
+}
+
+void push_result(uml_server* S, uml_fit_result& r, const Request& q) {
+  r.ticket = q.ticket;
+  r.latency_s = now_s() - q.t_submit;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->results.push_back(r);
+  S->finished++;
+  S->cv_result.notify_all();
+}
+
+// Places an admitted request in slot i: arena memory, upload, start metric.
+// Returns false (after queueing its result) when the fit is finished at once.
+int admit(uml_server* S, int i, size_t off, Request&& q, bool* started) {
+  const uml_model* m = S->m;
+  Slot& sl = S->slots[i];
+  *started = false;
+  sl.off = off;
+  sl.used = true;
+  sl.req = std::move(q);
+  sl.layout = data_layout(m->plan, sl.req.n, sl.req.weighted);
+  sl.o_work = round256(sl.layout.bytes_events);
+  sl.o_hess = sl.o_work + round256(sl.layout.bytes_work);
+  sl.data = uml_data();
+  data_bind(&sl.data, m, sl.req.n, sl.req.weighted, sl.layout, S->arena.at(sl.off),
+            S->arena.at(sl.off + sl.o_work));
+  sl.data.d_hwork = S->arena.at(sl.off + sl.o_hess);
+  hess_work_bytes(m, sl.req.n, &sl.data.hess_tiles);
+  sl.data.h_stage = S->h_stage;
+  sl.data.owns_memory = 0;
+  hipError_t e = data_upload(&sl.data, sl.layout, sl.req.host, S->stream);
+  if (e != hipSuccess) return set_error(UML_E_HIP, std::string("server upload: ") + hipGetErrorString(e));
+  std::vector<char>().swap(sl.req.host);  // the host copy is no longer needed
+  FitState F;
+  int rc = init_fit_state(m, &sl.data, sl.req.start.data(), S->opt.fit, F, S->stream, "server");
+  if (rc != UML_OK) return rc;
+  if (F.done) {  // P <= 0 at the start point
+    uml_fit_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.n_free = m->plan.nfree;
+    r.status = F.status;
+    r.nll = INFINITY;
+    for (int k = 0; k < m->plan.npar; ++k) r.params[k] = sl.req.start[k];
+    push_result(S, r, sl.req);
+    S->arena.release(sl.off, sl.req.bytes);
+    sl.used = false;
+    return UML_OK;
+  }
+  Job J = sl.data.job;
+  J.fit = S->d_fs + i;
+  J.theta = S->d_fs[i].theta;
+  J.out = S->d_fs[i].out;
+  S->jobs[i] = J;
+  UML_HIP_CHECK(hipMemcpyAsync(S->d_fs + i, &F, sizeof(FitState), hipMemcpyHostToDevice, S->stream));
+  UML_HIP_CHECK(hipMemcpyAsync(S->d_jobs + i, &J, sizeof(Job), hipMemcpyHostToDevice, S->stream));
+  *started = true;
+  return UML_OK;
+}
+
+// Retires slot i: final Hessian at the fitted point, result, memory.
+int retire(uml_server* S, int i) {
+  const uml_model* m = S->m;
+  const Plan& P = m->plan;
+  Slot& sl = S->slots[i];
+  FitState F;
+  UML_HIP_CHECK(hipMemcpyAsync(&F, S->d_fs + i, sizeof(FitState), hipMemcpyDeviceToHost, S->stream));
+  UML_HIP_CHECK(hipStreamSynchronize(S->stream));
+  uml_fit_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_free = P.nfree;
+  r.n_iter = F.n_iter;
+  r.n_eval = F.n_eval;
+  r.status = F.status;
+  std::vector<double> theta(F.theta, F.theta + P.npar);
+  if (r.status == UML_FIT_PDF_NONPOSITIVE) {
+    for (int k = 0; k < P.npar; ++k) r.params[k] = theta[k];
+    r.nll = INFINITY;
+  } else {
+    int rc = finish_fit(m, &sl.data, theta, S->opt.fit.polish, S->opt.fit.want_cov, &r, S->stream,
+                        "server");
+    if (rc != UML_OK) return rc;
+  }
+  push_result(S, r, sl.req);
+  S->arena.release(sl.off, sl.req.bytes);
+  sl.used = false;
+  return UML_OK;
+}
+
+void worker_main(uml_server* S) {
+  (void)hipSetDevice(S->m->device);
+  const uml_model* m = S->m;
+  std::vector<int2> map;
+  std::vector<int> done(S->slots.size(), 0);
+  bool dirty = true;
+  while (true) {
+    struct Intake {
+      int slot;
+      size_t off;
+      Request req;
+    };
+    std::vector<Intake> intake;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->stop && S->pending.empty() && S->active == 0) break;
+      // admission, in arrival order: a free slot and room in the arena (the
+      // memory budget); the arena belongs to this thread
+      for (int i = 0; i < int(S->slots.size()) && !S->pending.empty(); ++i) {
+        if (S->slots[i].used) continue;
+        size_t off = 0;
+        if (!S->arena.alloc(S->pending.front().bytes, &off)) break;
+        intake.push_back({i, off, std::move(S->pending.front())});
+        S->pending.pop_front();
+      }
+      if (intake.empty() && S->active == 0) {
+        S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+      S->admitted += int64_t(intake.size());
+    }
+    for (auto& in : intake) {
+      bool started = false;
+      const int64_t nb = int64_t(in.req.bytes);
+      int rc = admit(S, in.slot, in.off, std::move(in.req), &started);
+      if (rc != UML_OK) {
+        fail_worker(S, rc, uml_last_error());
+        return;
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (started) {
+        S->active++;
+        S->resident += nb;
+      }
+      dirty = true;
+    }
+    if (S->active == 0) continue;
+    if (dirty) {  // ragged tile map over the active fits
+      map.clear();
+      for (int i = 0; i < int(S->slots.size()); ++i)
+        if (S->slots[i].used)
+          for (int t = 0; t < S->slots[i].data.n_tiles; ++t) map.push_back(make_int2(i, t));
+      if (int(map.size()) > S->map_cap) {
+        fail_worker(S, UML_E_INVALID, "server: tile map capacity exceeded");
+        return;
+      }
+      hipError_t e = hipMemcpyAsync(S->d_map, map.data(), sizeof(int2) * map.size(),
+                                    hipMemcpyHostToDevice, S->stream);
+      if (e != hipSuccess) {
+        fail_worker(S, UML_E_HIP, hipGetErrorString(e));
+        return;
+      }
+      dirty = false;
+    }
+    const int grid = int(map.size());
+    if (grid != S->graph_grid) {  // capture kItersPerReplay iterations for this grid
+      if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+      if (S->graph) (void)hipGraphDestroy(S->graph);
+      S->gexec = nullptr;
+      S->graph = nullptr;
+      LaunchArgs a{};
+      a.job0 = S->jobs[0];
+      a.jobs = S->d_jobs;
+      a.tmap = S->d_map;
+      a.grid = grid;
+      a.precision = m->plan.precision;
+      a.stream = S->stream;
+      hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+      for (int k = 0; k < kItersPerReplay && e == hipSuccess; ++k) m->family->eval(a);
+      if (e == hipSuccess) e = hipStreamEndCapture(S->stream, &S->graph);
+      if (e == hipSuccess) e = hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        fail_worker(S, UML_E_HIP, std::string("server graph: ") + hipGetErrorString(e));
+        return;
+      }
+      S->graph_grid = grid;
+    }
+    hipError_t e = hipGraphLaunch(S->gexec, S->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(done.data(), sizeof(int), &S->d_fs[0].done, sizeof(FitState), sizeof(int),
+                           S->slots.size(), hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) {
+      fail_worker(S, UML_E_HIP, std::string("server iteration: ") + hipGetErrorString(e));
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->iterations += kItersPerReplay;
+    }
+    for (int i = 0; i < int(S->slots.size()); ++i) {
+      if (!S->slots[i].used || !done[i]) continue;
+      const int64_t nb = int64_t(S->slots[i].req.bytes);
+      int rc = retire(S, i);
+      if (rc != UML_OK) {
+        fail_worker(S, rc, uml_last_error());
+        return;
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->active--;
+      S->resident -= nb;
+      dirty = true;
+    }
+  }
+}
+
+}  // namespace
+}  // namespace uml
 
 extern "C" {
 
@@ -12,22 +379,151 @@ void uml_server_options_default(uml_server_options* o) {
   o->max_pending = 1 << 20;
   uml_fit_options_default(&o->fit);
 }
-int uml_server_create(const uml_model*, const uml_server_options*, uml_server** out) {
-  if (out) *out = nullptr;
-  return set_error(UML_E_UNSUPPORTED, "uml_server_create: not built yet");
+
+int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_server** out) {
+  if (!out || !m) return set_error(UML_E_INVALID, "uml_server_create: null argument");
+  *out = nullptr;
+  uml_server* S = new (std::nothrow) uml_server();
+  if (!S) return set_error(UML_E_NOMEM, "uml_server_create: out of host memory");
+  S->m = m;
+  uml_server_options_default(&S->opt);
+  if (opts) S->opt = *opts;
+  if (S->opt.max_slots <= 0) S->opt.max_slots = 256;
+  if (S->opt.hbm_budget <= 0) S->opt.hbm_budget = int64_t(4) << 30;
+  if (S->opt.max_pending <= 0) S->opt.max_pending = 1 << 20;
+  const int ns = S->opt.max_slots;
+  S->slots.resize(ns);
+  S->jobs.resize(ns);
+  // tile map capacity: the arena holds at most budget / (bytes of one tile)
+  const DataLayout one = data_layout(m->plan, 1, false);
+  const int64_t tile_bytes = int64_t(one.E) * kBlock * (m->plan.precision == UML_MIXED ? 4 : 8);
+  S->map_cap = int(std::min<int64_t>(S->opt.hbm_budget / std::max<int64_t>(tile_bytes, 1) + ns, 1 << 22));
+  auto fail = [&](hipError_t e, const char* what) {
+    if (S->arena_mem) (void)hipFree(S->arena_mem);
+    if (S->state_mem) (void)hipFree(S->state_mem);
+    if (S->h_stage) (void)hipHostFree(S->h_stage);
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+    return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
+                     std::string("uml_server_create: ") + what + ": " + hipGetErrorString(e));
+  };
+  hipError_t e = hipSetDevice(m->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return fail(e, "stream");
+  e = hipMalloc(&S->arena_mem, size_t(S->opt.hbm_budget));
+  if (e != hipSuccess) return fail(e, "arena");
+  const size_t o_jobs = round256(sizeof(FitState) * ns), o_map = o_jobs + round256(sizeof(Job) * ns);
+  e = hipMalloc(&S->state_mem, o_map + sizeof(int2) * size_t(S->map_cap));
+  if (e != hipSuccess) return fail(e, "fit states");
+  e = hipMemset(S->state_mem, 0, o_map);
+  if (e != hipSuccess) return fail(e, "fit states");
+  e = hipHostMalloc(reinterpret_cast<void**>(&S->h_stage), sizeof(double) * 4 * (UML_MAX_PARAMS + 2),
+                    hipHostMallocDefault);
+  if (e != hipSuccess) return fail(e, "pinned staging");
+  S->arena.init(static_cast<char*>(S->arena_mem), size_t(S->opt.hbm_budget));
+  S->d_fs = reinterpret_cast<FitState*>(S->state_mem);
+  S->d_jobs = reinterpret_cast<Job*>(static_cast<char*>(S->state_mem) + o_jobs);
+  S->d_map = reinterpret_cast<int2*>(static_cast<char*>(S->state_mem) + o_map);
+  // idle slots read as finished so that their (never mapped) tiles do nothing
+  std::vector<FitState> idle(ns);
+  for (auto& F : idle) {
+    std::memset(&F, 0, sizeof(F));
+    F.done = 1;
+  }
+  e = hipMemcpy(S->d_fs, idle.data(), sizeof(FitState) * ns, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(e, "fit states");
+  for (auto& J : S->jobs) std::memset(&J, 0, sizeof(J));
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return UML_OK;
 }
-int uml_server_submit(uml_server*, const uml_request*, uint64_t*) {
-  return set_error(UML_E_UNSUPPORTED, "uml_server_submit: not built yet");
+
+int uml_server_submit(uml_server* S, const uml_request* q, uint64_t* ticket) {
+  if (!S || !q || !ticket) return set_error(UML_E_INVALID, "uml_server_submit: null argument");
+  const Plan& P = S->m->plan;
+  Request r;
+  r.n = q->n_events;
+  r.weighted = q->w != nullptr;
+  int rc = convert_events(P, q->n_events, q->cols, q->dtype, q->w, r.host, "uml_server_submit");
+  if (rc != UML_OK) return rc;
+  r.start.resize(P.npar);
+  for (int k = 0; k < P.npar; ++k) r.start[k] = q->start ? q->start[k] : S->m->theta0[k];
+  r.bytes = request_bytes(S->m, r.n, r.weighted);
+  if (int64_t(r.bytes) > S->opt.hbm_budget)
+    return set_error(UML_E_BUDGET, "uml_server_submit: the request needs " +
+                                       std::to_string(r.bytes) + " bytes, more than the budget");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->worker_error) return set_error(S->worker_error, "uml_server_submit: " + S->worker_msg);
+  if (int64_t(S->pending.size()) >= S->opt.max_pending)
+    return set_error(UML_E_QUEUE_FULL, "uml_server_submit: too many pending requests");
+  r.ticket = S->next_ticket++;
+  r.t_submit = now_s();
+  *ticket = r.ticket;
+  S->pending.push_back(std::move(r));
+  S->submitted++;
+  S->cv_work.notify_one();
+  return UML_OK;
 }
-int uml_server_poll(uml_server*, uml_fit_result*, int32_t, int32_t*, int32_t) {
-  return set_error(UML_E_UNSUPPORTED, "uml_server_poll: not built yet");
+
+int uml_server_poll(uml_server* S, uml_fit_result* out, int32_t max, int32_t* n_out, int32_t timeout_us) {
+  if (!S || !n_out || (max > 0 && !out)) return set_error(UML_E_INVALID, "uml_server_poll: bad argument");
+  *n_out = 0;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto ready = [&] {
+    return !S->results.empty() || S->worker_error ||
+           (timeout_us < 0 && S->finished >= S->submitted);
+  };
+  if (timeout_us > 0)
+    S->cv_result.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+  else if (timeout_us < 0)
+    S->cv_result.wait(lk, ready);
+  while (*n_out < max && !S->results.empty()) {
+    out[(*n_out)++] = S->results.front();
+    S->results.pop_front();
+  }
+  if (S->worker_error) return set_error(S->worker_error, "uml_server_poll: " + S->worker_msg);
+  if (*n_out == 0 && timeout_us != 0) return set_error(UML_E_TIMEOUT, "uml_server_poll: no result");
+  return UML_OK;
 }
-int uml_server_stats_get(uml_server*, uml_server_stats*) {
-  return set_error(UML_E_UNSUPPORTED, "uml_server_stats_get: not built yet");
+
+int uml_server_stats_get(uml_server* S, uml_server_stats* st) {
+  if (!S || !st) return set_error(UML_E_INVALID, "uml_server_stats_get: null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  st->submitted = S->submitted;
+  st->admitted = S->admitted;
+  st->finished = S->finished;
+  st->pending = int64_t(S->pending.size());
+  st->active = S->active;
+  st->iterations = S->iterations;
+  st->resident_bytes = S->resident;
+  return UML_OK;
 }
-int uml_server_drain(uml_server*) {
-  return set_error(UML_E_UNSUPPORTED, "uml_server_drain: not built yet");
+
+int uml_server_drain(uml_server* S) {
+  if (!S) return set_error(UML_E_INVALID, "uml_server_drain: null argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  S->cv_result.wait(lk, [&] { return S->finished >= S->submitted || S->worker_error; });
+  if (S->worker_error) return set_error(S->worker_error, "uml_server_drain: " + S->worker_msg);
+  return UML_OK;
 }
-void uml_server_destroy(uml_server*) {}
+
+void uml_server_destroy(uml_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->pending.clear();
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->graph) (void)hipGraphDestroy(S->graph);
+  if (S->arena_mem) (void)hipFree(S->arena_mem);
+  if (S->state_mem) (void)hipFree(S->state_mem);
+  if (S->h_stage) (void)hipHostFree(S->h_stage);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  delete S;
+}
 
 }  // extern "C"

@@ -386,3 +386,60 @@ def uml_fit_batch(model, datas, starts=None, **opts):
 
 def uml_version():
     return lib().uml_version().decode()
+
+
+class Server:
+    """uml_server_*: a device-resident loop fitting many pseudo-experiments of
+    one model with continuous batching."""
+
+    def __init__(self, model, max_slots=256, hbm_budget=4 << 30, max_pending=1 << 20, **fit_opts):
+        o = uml_server_options()
+        lib().uml_server_options_default(C.byref(o))
+        o.max_slots, o.hbm_budget, o.max_pending = max_slots, hbm_budget, max_pending
+        o.fit = fit_options(**fit_opts)
+        h = _P()
+        check(lib().uml_server_create(model.handle, C.byref(o), C.byref(h)))
+        self.handle = h
+        self.model = model
+
+    def submit(self, events, weights=None, start=None):
+        """events: (n_dims, n) float32/float64 host array.  Returns the ticket."""
+        ev = np.ascontiguousarray(np.asarray(events))
+        if ev.ndim == 1:
+            ev = ev.reshape(1, -1)
+        if ev.dtype not in (np.float32, np.float64):
+            ev = ev.astype(np.float64)
+            ev = np.ascontiguousarray(ev)
+        cols = (C.c_void_p * ev.shape[0])(*[ev[d].ctypes.data for d in range(ev.shape[0])])
+        wt = None
+        if weights is not None:
+            wt = np.ascontiguousarray(np.asarray(weights, dtype=ev.dtype))
+        st = None if start is None else np.ascontiguousarray(start, dtype=np.float64)
+        q = uml_request(ev.shape[1], cols, UML_F32 if ev.dtype == np.float32 else UML_F64,
+                        None if wt is None else wt.ctypes.data, None if st is None else _dptr(st))
+        t = C.c_uint64()
+        check(lib().uml_server_submit(self.handle, C.byref(q), C.byref(t)))
+        return t.value
+
+    def poll(self, max_results=1024, timeout_us=0):
+        rs = (uml_fit_result * max_results)()
+        n = C.c_int32()
+        rc = lib().uml_server_poll(self.handle, rs, max_results, C.byref(n), timeout_us)
+        check(rc, allow=(UML_E_TIMEOUT,))
+        return [result_dict(self.model, rs[i]) for i in range(n.value)]
+
+    def drain(self):
+        check(lib().uml_server_drain(self.handle))
+
+    def stats(self):
+        st = uml_server_stats()
+        check(lib().uml_server_stats_get(self.handle, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in uml_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.uml_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
