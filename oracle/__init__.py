@@ -67,6 +67,8 @@ def _load():
         lib.orc_pdf.restype = None
         lib.orc_nll.argtypes = [C.POINTER(_Model), C.c_long, dp, dp, dp, C.c_int, dp, dp, dp]
         lib.orc_nll.restype = C.c_long
+        lib.orc_w2.argtypes = [C.POINTER(_Model), C.c_long, dp, dp, dp, dp]
+        lib.orc_w2.restype = C.c_long
         lib.orc_fit.argtypes = [C.POINTER(_Model), C.c_long, dp, dp, dp, ip,
                                 C.POINTER(_FitOpts), dp, C.POINTER(_FitInfo)]
         lib.orc_fit.restype = C.c_int
@@ -147,6 +149,21 @@ class Model:
         bad = _load().orc_nll(C.byref(self._m), n, _dptr(x), wp, _dptr(th), order,
                               C.byref(nll), _dptr(g), _dptr(h))
         return (nll.value, g if order >= 1 else None, h if order >= 2 else None, int(bad))
+
+    def w2(self, x, theta=None, w=None):
+        """W2 = sum_i w_i^2 s_i s_i^T over all parameters; returns (w2, n_bad)."""
+        x = _ncols(x, self.ndim)
+        n = x.shape[1]
+        th = np.ascontiguousarray(self.theta0 if theta is None else theta, dtype=np.float64)
+        wp = None
+        if w is not None:
+            w = np.ascontiguousarray(w, dtype=np.float64)
+            if w.shape != (n,):
+                raise ValueError("weights must have one entry per event")
+            wp = _dptr(w)
+        out = np.zeros((self.npar, self.npar))
+        bad = _load().orc_w2(C.byref(self._m), n, _dptr(x), wp, _dptr(th), _dptr(out))
+        return out, int(bad)
 
     def fit(self, x, start=None, free=None, w=None, edm_tol=1e-6, max_iter=500, polish=0):
         """BFGS fit; returns a dict with theta, errors, cov (free order), nll, edm ..."""

@@ -404,6 +404,37 @@ long orc_nll(const orc_model* m, long n, const double* x, const double* w,
   return bad;
 }
 
+/* Sum over events of w_i^2 s_i s_i^T with s_i = d ln P(x_i) / d theta
+   (all parameters): the variance of the weighted score, the middle factor
+   of the weighted-fit covariance H^-1 W2 H^-1.  Neumaier sums; any P <= 0
+   gives W2 = 0 and is counted in the return value. */
+long orc_w2(const orc_model* m, long n, const double* x, const double* w,
+            const double* theta, double* w2) {
+  int np = m->npar;
+  double* ss = (double*)calloc(2 * NP * NP, sizeof(double));
+  val_t* o = (val_t*)malloc(sizeof(val_t));
+  double xe[ORC_MAXD], sc[NP];
+  long bad = 0;
+  for (long i = 0; i < n; ++i) {
+    for (int d = 0; d < m->ndim; ++d) xe[d] = x[(long)d * n + i];
+    double wi = w ? w[i] : 1.0;
+    eval_node(m, m->root, xe, theta, 1, o);
+    double v = o->v;
+    if (!(v > 0.0) || !isfinite(v)) {
+      ++bad;
+      continue;
+    }
+    for (int a = 0; a < np; ++a) sc[a] = o->g[a] / v;
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < np; ++b)
+        nadd(&ss[a * np + b], &ss[NP * NP + a * np + b], wi * wi * sc[a] * sc[b]);
+  }
+  for (int a = 0; a < np * np; ++a) w2[a] = bad ? 0.0 : ss[a] + ss[NP * NP + a];
+  free(o);
+  free(ss);
+  return bad;
+}
+
 /* ------------------------------------------------------------------ */
 /* BFGS fit                                                            */
 /* ------------------------------------------------------------------ */

@@ -70,6 +70,11 @@ long orc_nll(const orc_model* m, long n, const double* x, const double* w,
              const double* theta, int order, double* nll, double* grad,
              double* hess);
 
+/* Weighted score variance W2 = sum_i w_i^2 s_i s_i^T, s_i = d ln P / d theta
+   (npar x npar, row-major); returns the count of events with P <= 0. */
+long orc_w2(const orc_model* m, long n, const double* x, const double* w,
+            const double* theta, double* w2);
+
 typedef struct {
   double edm_tol;  /* stop when 0.5 g^T V g < edm_tol                   */
   int max_iter;    /* BFGS iterations                                   */

@@ -392,6 +392,44 @@ def test_gradient_and_hessian_match_finite_differences(name, mk, gen, th, steps)
     assert np.allclose(h, h.T, rtol=1e-12, atol=1e-12 * np.max(np.abs(h)))
 
 
+@pytest.mark.parametrize("name,mk,gen,th,steps", FD_CASES[:2], ids=[c[0] for c in FD_CASES[:2]])
+def test_w2_matches_finite_difference_scores(name, mk, gen, th, steps):
+    """W2 = sum w^2 s s^T, with each event's score s = d ln P / d theta taken
+    by Richardson central differences of its log-density alone."""
+    m = oracle.Model(mk())
+    x = gen()
+    th = np.array(th, dtype=np.float64)
+    n = x.shape[1]
+    w = np.random.default_rng(3).uniform(0.5, 1.5, n)
+    w2, bad = m.w2(x, th, w)
+    assert bad == 0
+    S = np.stack([richardson_grad(lambda t: math.log(m.pdf(x[:, i:i + 1], t)[0]), th, np.array(steps))
+                  for i in range(n)])
+    w2_fd = (S.T * w ** 2) @ S
+    scale = np.sqrt(np.outer(np.diag(w2_fd), np.diag(w2_fd))) + 1e-300
+    assert np.max(np.abs(w2 - w2_fd) / scale) < 1e-6
+
+
+def test_sandwich_variance_of_weighted_gaussian_mean():
+    """Gauss with sigma fixed, far inside [5.0, 5.6]: the weighted MLE of mu is
+    the weighted mean, and H^-1 W2 H^-1 is sum w^2 (x - mu)^2 / (sum w)^2, the
+    usual variance estimate of a weighted mean."""
+    rng = np.random.default_rng(8)
+    n = 4000
+    x = rng.normal(5.28, 0.02, n).reshape(1, -1)
+    w = rng.uniform(0.5, 1.5, n)
+    desc = gauss_model(5.0, 5.6, 5.28, 0.02)
+    desc["params"][1]["fixed"] = True
+    m = oracle.Model(desc)
+    mu = math.fsum(w * x[0]) / math.fsum(w)
+    th = np.array([mu, 0.02])
+    _, g, h, _ = m.nll(x, th, w=w, order=2)
+    assert abs(g[0]) * 0.02 / math.sqrt(n) < 1e-9
+    w2, _ = m.w2(x, th, w)
+    var = w2[0, 0] / h[0, 0] ** 2
+    assert var == pytest.approx(math.fsum(w ** 2 * (x[0] - mu) ** 2) / math.fsum(w) ** 2, rel=1e-10)
+
+
 # --------------------------------------------------------------------------
 # weights, invalid points
 # --------------------------------------------------------------------------
