@@ -1,19 +1,29 @@
-"""Benchmark of the hot path: fused NLL + gradient evaluations per second.
+"""Benchmark of the hot path.
 
-A step is one evaluation of -sum_i ln P(x_i|theta) and its gradient over every
-event of one dataset (the per-minimiser-step work of an unbinned fit): the
-constant staging, the fused PDF/log/gradient event kernel, the deterministic
-two-pass reduction and the FP64 epilogue -- one kernel launch.  The workload
-is the 4-D angular x mass model (P-wave x Gauss signal, Chebyshev^3 x Exp
-background, 17 free parameters) at 1e6 synthetic events in mixed precision
-(FP32 per-event arithmetic, FP64 accumulation), events resident in HBM.
+Headline: fused NLL + gradient evaluations per second.  A step is one
+evaluation of -sum_i ln P(x_i|theta) and its gradient over every event of one
+dataset (the per-minimiser-step work of an unbinned fit): constant staging,
+the fused PDF/log/gradient event kernel, the deterministic two-pass reduction
+and the FP64 epilogue -- one kernel launch.  The workload is the 4-D angular x
+mass model (P-wave x Gauss signal, Chebyshev^3 x Exp background, 17 free
+parameters, mu fixed) at 1e6 synthetic events in mixed precision (FP32
+per-event arithmetic, FP64 accumulation), events resident in HBM.
+
+Serving: a toy study of the same model.  Requests of log-uniform size in
+[500, 50000] events arrive as a Poisson stream at 500 fits/s (open loop) or
+all at once (saturated); each is fitted from the generating values with BFGS
+to EDM < 1e-6 and its covariance taken from the analytic Hessian.  The batched
+server (continuous batching, memory-budget admission, graph replays) is
+compared with a loop that runs one fit after another through uml_fit.
 
 Prints one JSON line (see the repository's benchmark contract).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -21,14 +31,364 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Peaks derived in the design doc: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12
-# VALU lane-instructions/s; FP32 FMA = 2 FLOP -> 78.6 TFLOP/s without packed
-# FP32 (packed FP32 instructions are not used by this library).
-PEAK_FP32_UNPACKED_TFLOPS = 78.6
+# FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) = 78.6
+# TFLOP/s with one FP32 operation per lane and cycle.  The library is built
+# without packed FP32, whose 157.3 TFLOP/s is reported beside it.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP32 work per event of the 4-D model (counted from the fused
-# per-event formula in the design doc: FMA = 2, transcendental = 1).
-FLOP_PER_EVENT_4D = 145
+# Algorithmic FP32 work per event of the 4-D model: the operations of the
+# fused per-event formula (FMA and multiply-add count 2, every other
+# operation including each transcendental counts 1).
+FLOP_PER_EVENT_4D = 137
+
+# Sources of the event kernels: HBM traffic measured with hardware counters
+# (profiles/) is reported only while these are unchanged.
+KERNEL_SOURCES = ["paper_2505_12414_amd/csrc/eval.hip", "paper_2505_12414_amd/csrc/prologue.h",
+                  "paper_2505_12414_amd/csrc/devmath.h", "paper_2505_12414_amd/csrc/uml_internal.h"]
+COPY_MB = 512
+
+SEED_DATA = 20250512
+SEED_STREAM = 20250513
+SEED_POOL = 20250514
+SEED_TOY0 = 1_000_000
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(workload):
+    """HBM bytes per launch from the committed counter summary of this
+    workload, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(workload)
+    if not rec or rec.get("kernel_sources") != kernel_source_hash():
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
+
+
+def copy_check(torch, stream, reps=20):
+    """A plain device copy of known size (COPY_MB read + COPY_MB written per
+    launch, beyond the 256 MB last-level cache): the measured HBM rate, and
+    the calibration kernel for the hardware traffic counters."""
+    n = (COPY_MB << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            torch.add(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for _ in range(reps):
+            torch.add(src, 1.0, out=dst)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2 * (COPY_MB << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
+def headline(args, torch, uml, G, W):
+    n = args.events
+    dtype = np.float32 if args.precision == "mixed" else np.float64
+    if args.model == "angmass4d":
+        desc = W.angmass4d()
+        x = G.gen_angmass4d(n, seed=SEED_DATA, dtype=dtype)
+        truth = W.angmass4d_truth_vector()
+    else:
+        desc = W.mass1d()
+        x = G.gen_mass1d(n, seed=SEED_DATA, dtype=dtype)
+        truth = [5.28, 0.02, -1.5, 0.3]
+    dev = torch.device("cuda:0")
+    model = uml.Model(desc, args.precision)
+    data = uml.Data(model, x)
+    theta = torch.tensor(truth, dtype=torch.float64, device=dev)
+    out = torch.empty(1 + model.n_free, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    copy_gbs = copy_check(torch, stream)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            uml.uml_eval_nll_grad_dev(model, data, theta, out, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        ev0.record(stream)
+        for _ in range(args.steps):
+            uml.uml_eval_nll_grad_dev(model, data, theta, out, stream=stream)
+        ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)          # HIP events on the kernels' own stream
+    ms_per_step = gpu_ms / args.steps
+    value = n * args.steps / (gpu_ms * 1e-3)
+
+    esize = 4 if args.precision == "mixed" else 8
+    kname = f"eval_kernel ({args.model}, {args.precision})"
+    if args.model == "angmass4d" and args.precision == "mixed":
+        achieved = FLOP_PER_EVENT_4D * n / (ms_per_step * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                    "traffic": None, "kernel": kname, "flop_per_event": FLOP_PER_EVENT_4D,
+                    "frac_of_packed_fp32": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4),
+                    "bytes_per_event": 4 * esize}
+    elif args.model == "angmass4d":
+        achieved = FLOP_PER_EVENT_4D * n / (ms_per_step * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                    "traffic": None, "kernel": kname, "flop_per_event": FLOP_PER_EVENT_4D,
+                    "bytes_per_event": 4 * esize}
+    else:
+        achieved = esize * n / (ms_per_step * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                    "kernel": kname, "bytes_per_event": esize}
+    if args.model == "angmass4d" and args.marginal_events > n:
+        # the per-event cost alone: a second, larger dataset timed the same
+        # way; the difference removes the fixed cost of a launch (dispatch,
+        # constant check, reduction chain), which dominates at 1e6 events
+        n2 = args.marginal_events
+        x2 = G.gen_angmass4d(n2, seed=SEED_DATA + 1, dtype=dtype)
+        data2 = uml.Data(model, x2)
+        steps2 = max(10, args.steps // 4)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                uml.uml_eval_nll_grad_dev(model, data2, theta, out, stream=stream)
+            e2a, e2b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e2a.record(stream)
+            for _ in range(steps2):
+                uml.uml_eval_nll_grad_dev(model, data2, theta, out, stream=stream)
+            e2b.record(stream)
+        torch.cuda.synchronize()
+        us2 = e2a.elapsed_time(e2b) / steps2 * 1e3
+        us1 = ms_per_step * 1e3
+        per_event_s = (us2 - us1) * 1e-6 / (n2 - n)
+        peak = PEAK_FP32_TFLOPS if args.precision == "mixed" else PEAK_FP64_TFLOPS
+        tf = FLOP_PER_EVENT_4D / per_event_s / 1e12
+        roofline["marginal"] = {"events": [n, n2], "us_per_step": [round(us1, 3), round(us2, 3)],
+                                "fixed_us": round(us1 - n * per_event_s * 1e6, 3),
+                                "achieved": round(tf, 3), "frac": round(tf / peak, 4)}
+        del data2, x2
+    wl_key = f"{args.model}-{n}-{args.precision}"
+    traffic = counted_traffic(wl_key)
+    roofline["traffic"] = traffic
+    roofline["traffic_key"] = wl_key
+    roofline["measured_copy_gbs"] = round(copy_gbs, 1)
+    return {"desc": desc, "x": x, "truth": truth, "n": n, "model": model, "value": value,
+            "ms_per_step": ms_per_step, "wall": wall, "roofline": roofline,
+            "nll": float(out[0].item())}
+
+
+# ---------------------------------------------------------------------------
+# Serving toy study
+
+
+class Stream:
+    """The request stream: sizes, arrival times and events.  The first
+    n_indep requests carry independently generated events (seed SEED_TOY0+i)
+    and are the ones pulls are computed from; the others are seeded windows of
+    one large pool drawn from the same model."""
+
+    def __init__(self, args, G):
+        rng = np.random.default_rng(SEED_STREAM)
+        k = args.serving_fits
+        self.sizes = np.floor(np.exp(rng.uniform(np.log(500), np.log(50000), k))).astype(np.int64)
+        gaps = rng.exponential(1.0 / args.rate, k)
+        self.arrivals = np.cumsum(gaps) - gaps[0]
+        self.n_indep = min(args.pull_fits, k)
+        pool_n = max(args.pool_events, 60000)
+        self.pool = G.gen_angmass4d(pool_n, SEED_POOL, dtype=np.float32)
+        self.offsets = rng.integers(0, pool_n - 50000, k)
+        self.indep = [G.gen_angmass4d(int(self.sizes[i]), SEED_TOY0 + i, dtype=np.float32)
+                      for i in range(self.n_indep)]
+
+    def events(self, i):
+        if i < self.n_indep:
+            return self.indep[i]
+        o = int(self.offsets[i])
+        return self.pool[:, o:o + int(self.sizes[i])]
+
+
+def _pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def run_server(uml, um, st, k, open_loop, slots, budget):
+    srv = uml.Server(um, max_slots=slots, hbm_budget=budget)
+    t_recv, res = {}, {}
+    idx = {}
+    done = threading.Event()
+
+    def collect():
+        got = 0
+        while got < k:
+            rs = srv.poll(max_results=256, timeout_us=20000)
+            t = time.perf_counter()
+            for r in rs:
+                t_recv[r["ticket"]] = t
+                res[r["ticket"]] = r
+            got += len(rs)
+        done.set()
+
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    t0 = time.perf_counter()
+    for i in range(k):
+        if open_loop:
+            d = t0 + st.arrivals[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+        idx[srv.submit(st.events(i))] = i
+    th.join()
+    t_end = max(t_recv.values())
+    stats = srv.stats()
+    srv.close()
+    lat = np.empty(k)
+    out = [None] * k
+    for tk, i in idx.items():
+        lat[i] = t_recv[tk] - (t0 + (st.arrivals[i] if open_loop else 0.0))
+        out[i] = res[tk]
+    return {"fits_per_s": k / (t_end - t0), "p50_ms": 1e3 * _pct(lat, 50),
+            "p99_ms": 1e3 * _pct(lat, 99), "elapsed_s": t_end - t0, "stats": stats,
+            "results": out}
+
+
+def run_loop(uml, um, st, k, open_loop):
+    lat = np.empty(k)
+    out = []
+    t0 = time.perf_counter()
+    for i in range(k):
+        if open_loop:
+            d = t0 + st.arrivals[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+        data = uml.Data(um, st.events(i))
+        r = uml.uml_fit(um, data)
+        data.close()
+        t = time.perf_counter()
+        lat[i] = t - (t0 + (st.arrivals[i] if open_loop else 0.0))
+        out.append(r)
+    t_end = time.perf_counter()
+    return {"fits_per_s": k / (t_end - t0), "p50_ms": 1e3 * _pct(lat, 50),
+            "p99_ms": 1e3 * _pct(lat, 99), "elapsed_s": t_end - t0, "results": out}
+
+
+def pulls(results, truth, free):
+    ok = [r for r in results if r["status"] == 0]
+    if not ok:
+        return None
+    p = np.array([(r["theta"][free] - truth[free]) / r["errors"][free] for r in ok])
+    return {"fits": len(ok), "mean": [round(float(v), 3) for v in p.mean(0)],
+            "width": [round(float(v), 3) for v in p.std(0, ddof=1)] if len(ok) > 1 else None}
+
+
+def serving(args, uml, G, W):
+    desc = W.angmass4d()
+    um = uml.Model(desc, "mixed")
+    truth = np.array(W.angmass4d_truth_vector())
+    free = np.array([not p.get("fixed", False) for p in desc["params"]])
+    st = Stream(args, G)
+    k = args.serving_fits
+    kl = min(args.loop_fits, k)
+    budget = args.budget_mb << 20
+    s_open = run_server(uml, um, st, k, True, args.slots, budget)
+    s_sat = run_server(uml, um, st, k, False, args.slots, budget)
+    l_sat = run_loop(uml, um, st, kl, False)
+    l_open = run_loop(uml, um, st, kl, True)
+    # equal accuracy: the fits of both paths on the requests both ran
+    dev = 0.0
+    for a, b in zip(s_sat["results"][:kl], l_sat["results"]):
+        if a["status"] == 0 and b["status"] == 0:
+            dev = max(dev, float(np.max(np.abs(a["theta"][free] - b["theta"][free])
+                                        / b["errors"][free])))
+    statuses = {}
+    for r in s_sat["results"]:
+        statuses[r["status_name"]] = statuses.get(r["status_name"], 0) + 1
+
+    def summary(d):
+        o = {key: round(d[key], 3) for key in ("fits_per_s", "p50_ms", "p99_ms", "elapsed_s")}
+        if "stats" in d:
+            s = d["stats"]
+            o["peak_resident_mb"] = round(s["peak_resident_bytes"] / 2**20, 1)
+            o["budget_waits"] = s["budget_waits"]
+            o["iterations"] = s["iterations"]
+        return o
+
+    return {"desc": desc, "stream": st, "truth": truth, "free": free,
+            "server_results": s_open["results"],
+            "record": {
+                "workload": (f"4-D toy fits, sizes log-uniform in [500, 50000], Poisson arrivals "
+                             f"at {args.rate:g}/s, mixed precision, start at the generating values, "
+                             "EDM < 1e-6"),
+                "fits": k, "loop_fits": kl, "slots": args.slots, "hbm_budget_mb": args.budget_mb,
+                "server_open_loop": summary(s_open), "server_saturated": summary(s_sat),
+                "loop_open_loop": summary(l_open), "loop_saturated": summary(l_sat),
+                "capacity_ratio": round(s_sat["fits_per_s"] / l_sat["fits_per_s"], 2),
+                "max_dtheta_over_sigma_server_vs_loop": dev,
+                "statuses": statuses,
+                "pulls": pulls(s_open["results"][:st.n_indep], truth, free),
+                "events": ("first %d requests independently generated (seed %d+i); the rest are "
+                           "seeded windows of a %d-event pool from the same model"
+                           % (st.n_indep, SEED_TOY0, st.pool.shape[1]))}}
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on a bounded sample of the same work
+
+
+def cpu_baseline(args, H, S):
+    import oracle
+    om = oracle.Model(H["desc"])
+    k = min(H["n"], 100_000)
+    xs = H["x"][:, :k].astype(np.float64)
+    th = np.array(H["truth"])
+    reps, t = 0, 0.0
+    t0 = time.perf_counter()
+    while t < args.cpu_seconds:
+        om.nll(xs, th, order=1)
+        reps += 1
+        t = time.perf_counter() - t0
+    base = {"value": round(k * reps / t, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} events of the benchmark dataset, NLL+gradient, {reps} evaluations "
+                      f"in {t:.1f} s, one thread"}
+    if S is None:
+        return base, None
+    # the oracle's own fits of the independently generated toys, in order,
+    # for a bounded time; compared with the server's fits of the same toys
+    st, free = S["stream"], S["free"]
+    om4 = oracle.Model(S["desc"])
+    n_fit, t, dmax, emax, nev = 0, 0.0, 0.0, 0.0, 0
+    t0 = time.perf_counter()
+    while n_fit < st.n_indep and t < args.cpu_seconds:
+        x = st.indep[n_fit].astype(np.float64)
+        r = om4.fit(x, S["truth"])
+        g = S["server_results"][n_fit]
+        if r["status"] == 0 and g["status"] == 0:
+            sig = r["errors"]
+            dmax = max(dmax, float(np.max(np.abs(g["theta"][free] - r["theta"][free]) / sig)))
+            emax = max(emax, float(np.max(np.abs(g["errors"][free] - sig) / sig)))
+        nev += x.shape[1]
+        n_fit += 1
+        t = time.perf_counter() - t0
+    fits = {"value": round(n_fit / t, 2), "unit": "fits/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_fit} independently generated toys ({nev} events), FP64 BFGS "
+                      f"to EDM < 1e-6 and Hessian, {t:.1f} s, one thread",
+            "max_dtheta_over_sigma_vs_server": dmax,
+            "max_rel_error_of_sigma_vs_server": emax}
+    return base, fits
 
 
 def main():
@@ -39,11 +399,23 @@ def main():
     ap.add_argument("--events", type=int, default=1_000_000)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--model", default="angmass4d", choices=["angmass4d", "mass1d"])
+    ap.add_argument("--serving-fits", type=int, default=20000,
+                    help="requests in the toy study (0: skip it)")
+    ap.add_argument("--loop-fits", type=int, default=5000,
+                    help="requests of the same stream run through the per-fit loop")
+    ap.add_argument("--rate", type=float, default=500.0, help="open-loop arrival rate, fits/s")
+    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--budget-mb", type=int, default=256, help="server device-memory budget")
+    ap.add_argument("--pull-fits", type=int, default=200)
+    ap.add_argument("--pool-events", type=int, default=1 << 22)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--marginal-events", type=int, default=4_000_000,
+                    help="second dataset size for the per-event (marginal) rate; 0: skip")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU path is a design in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py: this implementation runs on one GPU (asked for {args.gpus}); "
+              "how the path would shard over several is described in DESIGN.md.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -51,94 +423,37 @@ def main():
     from paper_2505_12414_amd import uml
     from paper_2505_12414_amd import workloads as W
 
-    n = args.events
-    dtype = np.float32 if args.precision == "mixed" else np.float64
-    if args.model == "angmass4d":
-        desc = W.angmass4d()
-        x = G.gen_angmass4d(n, seed=20250512, dtype=dtype)
-        truth = W.angmass4d_truth_vector()
-    else:
-        desc = W.mass1d()
-        x = G.gen_mass1d(n, seed=20250512, dtype=dtype)
-        truth = [5.28, 0.02, -1.5, 0.3]
     torch.cuda.init()
-    dev = torch.device("cuda:0")
-    model = uml.Model(desc, args.precision)
-    data = uml.Data(model, x)
-    theta = torch.tensor(truth, dtype=torch.float64, device=dev)
-    out = torch.empty(1 + model.n_free, dtype=torch.float64, device=dev)
-    stream = torch.cuda.Stream(device=dev)
-
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            uml.uml_eval_nll_grad_dev(model, data, theta, out, stream=stream)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        ev0.record(stream)
-        for _ in range(args.steps):
-            uml.uml_eval_nll_grad_dev(model, data, theta, out, stream=stream)
-        ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)          # HIP events on the kernels' stream
-    ms_per_step = gpu_ms / args.steps
-    value = n * args.steps / (gpu_ms * 1e-3)
-    nll = float(out[0].item())
-
-    esize = 4 if args.precision == "mixed" else 8
-    kname = f"eval_kernel<{args.model}, {args.precision}>"
-    if args.model == "angmass4d":
-        flop = FLOP_PER_EVENT_4D * n
-        achieved = flop / (ms_per_step * 1e-3) / 1e12
-        roofline = {"bound": "alu", "achieved": round(achieved, 3),
-                    "peak": PEAK_FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4), "traffic": None,
-                    "kernel": kname, "flop_per_event": FLOP_PER_EVENT_4D,
-                    "bytes_per_event": 4 * esize}
-    else:
-        nbytes = esize * n
-        achieved = nbytes / (ms_per_step * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                    "kernel": kname, "bytes_per_event": esize}
-
-    cpu = None
+    H = headline(args, torch, uml, G, W)
+    print(f"# headline done: {H['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+    S = None
+    if args.serving_fits > 0:
+        S = serving(args, uml, G, W)
+        print("# serving done", file=sys.stderr, flush=True)
+    cpu, cpu_fits = (None, None)
     if not args.no_cpu_baseline:
-        import oracle
-        om = oracle.Model(desc)
-        k = min(n, 100_000)
-        xs = x[:, :k].astype(np.float64)
-        th = np.array(truth)
-        reps, t = 0, 0.0
-        t0 = time.perf_counter()
-        while t < 10.0:
-            om.nll(xs, th, order=1)
-            reps += 1
-            t = time.perf_counter() - t0
-        cpu = {"value": round(k * reps / t, 1), "unit": "events/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{k} events of the same dataset, NLL+gradient, {reps} evaluations, "
-                         f"{t:.1f} s, single thread"}
+        cpu, cpu_fits = cpu_baseline(args, H, S)
 
-    metric = ("NLL+grad events/s at 1e6 events (4D)" if args.model == "angmass4d"
-              else "NLL+grad events/s (1D mass model)")
-    wl = ("4-D angular x mass NLL+gradient" if args.model == "angmass4d"
-          else "1-D mass-model NLL+gradient")
-    rec = {"metric": metric, "value": round(value, 1),
-           "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(ms_per_step, 6), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32" if args.precision == "mixed" else "f64",
-           "data": "synthetic",
-           "config": {"workload": f"{wl}, {n} events, "
-                                  f"{'FP32 compute / FP64 accumulate' if args.precision == 'mixed' else 'FP64'}",
-                      "events": n, "free_params": model.n_free, "precision": args.precision},
-           "roofline": roofline, "cpu_baseline": cpu,
-           "nll": nll, "wall_s": round(wall, 4)}
+    if args.model == "angmass4d":
+        metric = "NLL+grad events/s at 1e6 events (4D); toy fits/s with p50/p99 latency"
+        wl = "4-D angular x mass NLL+gradient"
+    else:
+        metric = "NLL+grad events/s (1D mass model)"
+        wl = "1-D mass-model NLL+gradient"
+    prec = "FP32 compute / FP64 accumulate" if args.precision == "mixed" else "FP64"
+    rec = {"metric": metric, "value": round(H["value"], 1), "unit": "events/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(H["ms_per_step"], 6), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if args.precision == "mixed" else "f64", "data": "synthetic",
+           "config": {"workload": f"{wl}, {H['n']} events, {prec}", "events": H["n"],
+                      "free_params": H["model"].n_free, "precision": args.precision},
+           "roofline": H["roofline"], "cpu_baseline": cpu,
+           "nll": H["nll"], "wall_s": round(H["wall"], 4)}
+    if S is not None:
+        rec["serving"] = S["record"]
+        if cpu_fits is not None:
+            rec["serving"]["cpu_baseline"] = cpu_fits
     print(json.dumps(rec), flush=True)
 
 

@@ -170,8 +170,18 @@ typedef struct {
   double edm_tol;    /* stop when EDM = 0.5 g^T V g < edm_tol (default 1e-6) */
   int32_t max_iter;  /* BFGS iterations (default 1000)                        */
   int32_t polish;    /* Newton steps with the analytic Hessian after BFGS      */
-  int32_t want_cov;  /* compute the covariance (inverse Hessian) at the end    */
+  int32_t want_cov;  /* return the covariance matrix in uml_fit_result.cov    */
+  int32_t cov_kind;  /* UML_COV_HESSE: H^-1; UML_COV_SANDWICH: H^-1 W2 H^-1,
+                        W2 = sum w_i^2 s_i s_i^T (the covariance of weighted
+                        fits, Sec. 2.2); errors follow the chosen matrix      */
+  int32_t method;    /* UML_METHOD_BFGS: quasi-Newton steps on the device, one
+                        event pass per step; UML_METHOD_NEWTON: Newton steps
+                        with the analytic Hessian (one Hessian pass per
+                        iteration, host-driven; few iterations, Sec. 3.2)   */
 } uml_fit_options;
+
+enum { UML_COV_HESSE = 0, UML_COV_SANDWICH = 1 };
+enum { UML_METHOD_BFGS = 0, UML_METHOD_NEWTON = 1 };
 
 /* Fit status */
 enum {
@@ -231,7 +241,9 @@ typedef struct {
 typedef struct {
   int64_t submitted, admitted, finished, pending, active;
   int64_t iterations;      /* launches of the batched iteration              */
-  int64_t resident_bytes;  /* event storage currently resident               */
+  int64_t resident_bytes;  /* device bytes held by admitted requests          */
+  int64_t peak_resident_bytes;
+  int64_t budget_waits;    /* admission passes that stopped for lack of memory */
 } uml_server_stats;
 
 void uml_server_options_default(uml_server_options* o);

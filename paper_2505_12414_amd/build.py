@@ -19,13 +19,18 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+# Device code: callee-saved registers of the few out-of-line device functions
+# (constant prologue, BFGS step) are saved to scratch, not to accumulation
+# registers, which would otherwise add to every event kernel's register count
+# and cost it a wave per SIMD.
+HIP_FLAGS = ["-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
 SOURCES = ["eval.hip", "hess.hip", "bfgs.hip", "model.cpp", "api.cpp", "fit.cpp", "server.cpp"]
 
 
 def _compile(src, verbose):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJ, src + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    lang = ["-x", "hip"] + HIP_FLAGS if src.endswith(".hip") else []
     cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,37 @@ int set_error(int code, const std::string& msg) {
 }
 
 static int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Pinned host staging blocks of datasets (parameter vectors going up,
+// results coming down), carved from pinned allocations of 256 blocks that
+// live until the process ends: creating a dataset does not pay for a pinned
+// allocation, which is slow.
+namespace {
+constexpr size_t kStageBytes = 1152;  // >= 4 (UML_MAX_PARAMS + 2) doubles, 128-byte multiple
+static_assert(kStageBytes >= sizeof(double) * 4 * (UML_MAX_PARAMS + 2), "staging block too small");
+std::mutex g_stage_mu;
+std::vector<double*> g_stage_free;
+}  // namespace
+
+double* pinned_stage_get() {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (g_stage_free.empty()) {
+    constexpr int kBlocks = 256;
+    char* p = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), kStageBytes * kBlocks, hipHostMallocDefault) !=
+        hipSuccess)
+      return nullptr;
+    for (int i = kBlocks - 1; i >= 0; --i) g_stage_free.push_back(reinterpret_cast<double*>(p + i * kStageBytes));
+  }
+  double* b = g_stage_free.back();
+  g_stage_free.pop_back();
+  return b;
+}
+
+void pinned_stage_put(double* p) {
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  g_stage_free.push_back(p);
+}
 
 int convert_events(const Plan& P, int64_t n, const void* const* cols, int32_t dtype, const void* w,
                    std::vector<char>& host, const char* fn) {
@@ -179,6 +211,7 @@ void uml_model_destroy(uml_model* m) {
   if (!m) return;
   if (m->d_plan) (void)hipFree(m->d_plan);
   if (m->d_hplan) (void)hipFree(m->d_hplan);
+  if (m->d_fitws) (void)hipFree(m->d_fitws);
   delete m;
 }
 
@@ -229,24 +262,26 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
   uml_data* d = new (std::nothrow) uml_data();
   if (!d) return set_error(UML_E_NOMEM, "uml_data_create: out of host memory");
   auto fail = [&](hipError_t e, const char* what) {
-    if (d->d_events) (void)hipFree(d->d_events);
-    if (d->d_work) (void)hipFree(d->d_work);
-    if (d->h_stage) (void)hipHostFree(d->h_stage);
+    if (d->d_alloc) (void)hipFree(d->d_alloc);
+    if (d->h_stage) pinned_stage_put(d->h_stage);
     delete d;
     return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
                      std::string("uml_data_create: ") + what + ": " + hipGetErrorString(e));
   };
-  void *dev_ev = nullptr, *dev_work = nullptr;
-  hipError_t e = hipMalloc(&dev_ev, L.bytes_events);
-  if (e != hipSuccess) return fail(e, "event buffer");
-  d->d_events = dev_ev;
-  e = hipMalloc(&dev_work, L.bytes_work);
-  if (e != hipSuccess) return fail(e, "work buffer");
-  d->d_work = dev_work;
-  e = hipHostMalloc(reinterpret_cast<void**>(&d->h_stage), sizeof(double) * 4 * (UML_MAX_PARAMS + 2),
-                    hipHostMallocDefault);
-  if (e != hipSuccess) return fail(e, "pinned staging");
-  data_bind(d, m, n, w != nullptr, L, dev_ev, dev_work);
+  // one device allocation: events | work area | Hessian workspace
+  int hess_tiles = 0;
+  const size_t o_work = align_up(L.bytes_events, 256), o_hess = o_work + align_up(L.bytes_work, 256);
+  const size_t hbytes = m->d_hplan ? hess_work_bytes(m, n, &hess_tiles) : 0;
+  hipError_t e = hipMalloc(&d->d_alloc, o_hess + hbytes);
+  if (e != hipSuccess) return fail(e, "device buffer");
+  char* base = static_cast<char*>(d->d_alloc);
+  d->h_stage = pinned_stage_get();
+  if (!d->h_stage) return fail(hipErrorOutOfMemory, "pinned staging");
+  data_bind(d, m, n, w != nullptr, L, base, base + o_work);
+  if (hbytes) {
+    d->d_hwork = base + o_hess;
+    d->hess_tiles = hess_tiles;
+  }
   e = data_upload(d, L, host, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(e, "upload");
@@ -258,10 +293,8 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
 void uml_data_destroy(uml_data* d) {
   if (!d) return;
   if (d->owns_memory) {
-    if (d->d_events) (void)hipFree(d->d_events);
-    if (d->d_work) (void)hipFree(d->d_work);
-    if (d->d_hwork) (void)hipFree(d->d_hwork);
-    if (d->h_stage) (void)hipHostFree(d->h_stage);
+    if (d->d_alloc) (void)hipFree(d->d_alloc);
+    if (d->h_stage) pinned_stage_put(d->h_stage);
   }
   delete d;
 }

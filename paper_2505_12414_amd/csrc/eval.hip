@@ -351,33 +351,57 @@ template <class T, int VW>
 struct Vec;
 template <>
 struct Vec<float, 4> {
-  using type = float4;
+  typedef float type __attribute__((ext_vector_type(4)));
 };
 template <>
 struct Vec<double, 2> {
-  using type = double2;
+  typedef double type __attribute__((ext_vector_type(2)));
 };
+
+// Event columns live in device global memory: loads through global-space
+// pointers compile to global (not flat) vector loads.
+template <class T>
+__device__ __forceinline__ T load_global(const T* p) {
+  return *(__attribute__((address_space(1))) const T*)(p);
+}
 
 template <class T, int VW>
 __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&out)[VW]) {
   using V = typename Vec<T, VW>::type;
-  const V v = *reinterpret_cast<const V*>(p);
-  if constexpr (VW == 4) {
-    out[0] = v.x;
-    out[1] = v.y;
-    out[2] = v.z;
-    out[3] = v.w;
-  } else {
-    out[0] = v.x;
-    out[1] = v.y;
+  const V v = load_global(reinterpret_cast<const V*>(p));
+#pragma unroll
+  for (int q = 0; q < VW; ++q) out[q] = v[q];
+}
+
+// The first group of a full tile's events (VW per thread), loaded ahead of
+// the constant check so that the two latencies overlap.
+template <class S, class P>
+struct FirstGroup {
+  typename P::T x[P::VW][S::ndim];
+  typename P::T w[P::VW];
+};
+
+template <class S, class P>
+__device__ __forceinline__ void load_first_group(const Job& J, int64_t base, FirstGroup<S, P>& f) {
+  using T = typename P::T;
+  constexpr int VW = P::VW;
+  const int64_t e0 = base + int64_t(VW) * threadIdx.x;
+#pragma unroll
+  for (int d = 0; d < S::ndim; ++d) {
+    T tmp[VW];
+    load_vec<T, VW>(static_cast<const T*>(J.col[d]) + e0, tmp);
+#pragma unroll
+    for (int q = 0; q < VW; ++q) f.x[q][d] = tmp[q];
   }
+  if (J.w) load_vec<T, VW>(static_cast<const T*>(J.w) + e0, f.w);
 }
 
 template <class S, class P, bool W, bool FULL>
 __device__ __forceinline__ void process_tile(const Job& J, int64_t base,
                                              const typename P::T (&c)[S::ncst],
                                              const typename P::T (&xref)[S::ndim],
-                                             typename P::T (&acc)[S::K]) {
+                                             typename P::T (&acc)[S::K],
+                                             const FirstGroup<S, P>& first) {
   using T = typename P::T;
   constexpr int VW = P::VW;
   const int groups = J.events_per_thread / VW;
@@ -391,21 +415,30 @@ __device__ __forceinline__ void process_tile(const Job& J, int64_t base,
     T xv[VW][S::ndim];
     T wv[VW];
     if constexpr (FULL) {
+      if (g == 0) {
 #pragma unroll
-      for (int d = 0; d < S::ndim; ++d) {
-        T tmp[VW];
-        load_vec<T, VW>(col[d] + e0, tmp);
+        for (int q = 0; q < VW; ++q) {
 #pragma unroll
-        for (int q = 0; q < VW; ++q) xv[q][d] = tmp[q];
+          for (int d = 0; d < S::ndim; ++d) xv[q][d] = first.x[q][d];
+          if constexpr (W) wv[q] = first.w[q];
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < S::ndim; ++d) {
+          T tmp[VW];
+          load_vec<T, VW>(col[d] + e0, tmp);
+#pragma unroll
+          for (int q = 0; q < VW; ++q) xv[q][d] = tmp[q];
+        }
+        if constexpr (W) load_vec<T, VW>(wcol + e0, wv);
       }
-      if constexpr (W) load_vec<T, VW>(wcol + e0, wv);
     } else {
 #pragma unroll
       for (int q = 0; q < VW; ++q) {
         const bool ok = e0 + q < n;
 #pragma unroll
-        for (int d = 0; d < S::ndim; ++d) xv[q][d] = ok ? col[d][e0 + q] : T(0);
-        if constexpr (W) wv[q] = ok ? wcol[e0 + q] : T(0);
+        for (int d = 0; d < S::ndim; ++d) xv[q][d] = ok ? load_global(col[d] + e0 + q) : T(0);
+        if constexpr (W) wv[q] = ok ? load_global(wcol + e0 + q) : T(0);
       }
     }
 #pragma unroll
@@ -437,13 +470,23 @@ __device__ __forceinline__ void epilogue(const Plan& P, const ConstBlock* cb,
   }
 }
 
-// Bulk copy of n bytes (a multiple of 16, both 16-byte aligned) by the
-// whole workgroup: every load is issued before any is waited for.
-__device__ __forceinline__ void bulk_copy16(void* dst, const void* src, int nbytes) {
+// Bulk copy of n bytes (a multiple of 16, both 16-byte aligned) by
+// `threads` threads, this one being number `t`: every load is issued before
+// any is waited for.
+__device__ __forceinline__ void bulk_copy16(void* dst, const void* src, int nbytes, int t = threadIdx.x,
+                                            int threads = kBlock) {
   const int4* s4 = static_cast<const int4*>(src);
   int4* d4 = static_cast<int4*>(dst);
   const int n = nbytes / 16;
-  for (int i = threadIdx.x; i < n; i += kBlock) d4[i] = s4[i];
+  for (int i = t; i < n; i += threads) d4[i] = s4[i];
+}
+
+// Threads per column of column_sums, and the threads it occupies.
+template <int K>
+__host__ __device__ constexpr int column_q() {
+  int q = 1;
+  while (q * 2 * K <= kBlock && q * 2 <= 16) q *= 2;
+  return q;
 }
 
 // Fixed-order sums of column k (columns col_stride apart) over `count`
@@ -455,11 +498,7 @@ __device__ __forceinline__ void bulk_copy16(void* dst, const void* src, int nbyt
 template <int K>
 __device__ __forceinline__ void column_sums(double* base, int col_stride, int count, int step,
                                             double* lds, double* out) {
-  constexpr int Q = [] {
-    int q = 1;
-    while (q * 2 * K <= kBlock && q * 2 <= 16) q *= 2;
-    return q;
-  }();
+  constexpr int Q = column_q<K>();
   const int tid = threadIdx.x;
   if (tid < K * Q) {
     const int k = tid / Q, j = tid % Q;
@@ -704,6 +743,12 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   // (scalar loads, issued together with the comparison); otherwise the first
   // lane computes them here in FP64 (the prologue: normalisations, combined
   // prefactors, angular coefficients).
+  const int64_t tsize = int64_t(J.events_per_thread) * kBlock;
+  const int64_t base = int64_t(tile) * tsize;
+  const bool full = base + tsize <= J.n;
+  FirstGroup<S, P> first;
+  if (full) load_first_group<S, P>(J, base, first);
+
   const ConstBlock* __restrict__ gc = J.cst;
   T c[S::ncst];
 #pragma unroll
@@ -727,19 +772,16 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
-  const int64_t tsize = int64_t(J.events_per_thread) * kBlock;
-  const int64_t base = int64_t(tile) * tsize;
-  const bool full = base + tsize <= J.n;
   if (J.w) {
     if (full)
-      process_tile<S, P, true, true>(J, base, c, xref, acc);
+      process_tile<S, P, true, true>(J, base, c, xref, acc, first);
     else
-      process_tile<S, P, true, false>(J, base, c, xref, acc);
+      process_tile<S, P, true, false>(J, base, c, xref, acc, first);
   } else {
     if (full)
-      process_tile<S, P, false, true>(J, base, c, xref, acc);
+      process_tile<S, P, false, true>(J, base, c, xref, acc, first);
     else
-      process_tile<S, P, false, false>(J, base, c, xref, acc);
+      process_tile<S, P, false, false>(J, base, c, xref, acc, first);
   }
 
   // pass 1: lanes -> tile partial, through LDS in a fixed order
@@ -748,7 +790,8 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   constexpr int CH = kBlock / PARTS;
   // T-sized transpose buffer, reused afterwards for K + UML_MAX_PARAMS
   // doubles followed by the plan
-  constexpr int PASS2_BYTES = (K + UML_MAX_PARAMS) * sizeof(double) + sizeof(Plan) + 16;
+  constexpr int PASS2_BYTES =
+      (K + UML_MAX_PARAMS) * sizeof(double) + sizeof(Plan) + sizeof(ConstBlock) + 16;
   constexpr int LDS_T = (K * STRIDE * sizeof(T) > PASS2_BYTES) ? K * STRIDE
                                                                : int(PASS2_BYTES / sizeof(T)) + 4;
   __shared__ __align__(16) T red[LDS_T];
@@ -813,13 +856,22 @@ top_level:
   }
   __syncthreads();
   if (!s_flag) return;
-  // the last group: the plan, the constants to keep, the sum over groups
+  // The last group: the sum over groups, the plan and the constants.  The
+  // threads the column sums leave idle fetch the plan (and the cached
+  // constants) meanwhile, so the three reads cost one round trip.
   Plan* s_plan = reinterpret_cast<Plan*>(tot + ((K + UML_MAX_PARAMS + 1) & ~1));  // 16-byte aligned
-  bulk_copy16(s_plan, J.plan, int(sizeof(Plan)));
-  const ConstBlock* cb = hit ? gc : &s_cb;
+  ConstBlock* s_gc = reinterpret_cast<ConstBlock*>(reinterpret_cast<char*>(s_plan) + sizeof(Plan));
+  constexpr int QS = K * column_q<K>();
+  constexpr bool spare = kBlock - QS >= 64;
+  if (spare ? tid >= QS : true) {
+    const int t = spare ? tid - QS : tid, nt2 = spare ? kBlock - QS : kBlock;
+    bulk_copy16(s_plan, J.plan, int(sizeof(Plan)), t, nt2);
+    if (hit) bulk_copy16(s_gc, gc, int(sizeof(ConstBlock)), t, nt2);
+  }
   if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
-  column_sums<K>(gpart, kGroups, ng, 1, red2, tot);
-  epilogue(*s_plan, cb, tot, (out_override && !tmap) ? out_override : J.out);
+  if (!spare) __syncthreads();
+  column_sums<K>(gpart, kGroups, ng, 1, red2, tot);  // ends with a barrier
+  epilogue(*s_plan, hit ? s_gc : &s_cb, tot, (out_override && !tmap) ? out_override : J.out);
   if (J.fit) {
     __syncthreads();
     bfgs_step(*s_plan, J.fit, J.cst);

@@ -10,7 +10,14 @@ using namespace uml;
 
 namespace uml {
 
-constexpr int64_t kHessTileEvents = 4096;
+// Events per Hessian tile: a pure function of n (so is the reduction order),
+// small enough to spread a toy-sized dataset over many workgroups (at least
+// 256 events, one tile per 256 events up to 65536 events), at most 4096.
+static int64_t hess_tile_events(int64_t n) {
+  int64_t t = 256;
+  while (t < 4096 && t * 256 < n) t *= 2;
+  return t;
+}
 
 // Hessian workspace: constants | hc | out | partials.
 struct HessLayout {
@@ -20,7 +27,8 @@ struct HessLayout {
 static HessLayout hess_layout(const uml_model* m, int64_t n) {
   HessLayout L{};
   L.M = 1 + m->plan.nfree + 2 * m->hplan.npairs;
-  L.n_tiles = int(std::max<int64_t>(1, (n + kHessTileEvents - 1) / kHessTileEvents));
+  const int64_t te = hess_tile_events(n);
+  L.n_tiles = int(std::max<int64_t>(1, (n + te - 1) / te));
   L.o_cb = 0;
   L.o_hc = (sizeof(ConstBlock) + 255) / 256 * 256;
   L.o_out = L.o_hc + 256 * ((sizeof(double) * 4 * kMaxFac + 255) / 256);
@@ -35,11 +43,15 @@ size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles) {
   return L.bytes;
 }
 
-// Runs the Hessian pass for theta (host) and returns the raw sums
-// [sum w log2 P, sum w s (nfree), H pairs, W2 pairs].
-int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
-                 std::vector<double>& out, const char* fn) {
-  if (!m || !d || !theta) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+int hess_sums(const uml_model* m) { return 1 + m->plan.nfree + 2 * m->hplan.npairs; }
+
+// Queues the Hessian pass at the device parameter vector d_theta on stream s;
+// the raw sums [sum w log2 P, sum w s (nfree), H pairs, W2 pairs] are copied
+// to h_out (host; pinned memory keeps the call asynchronous) when the stream
+// gets there.
+int hessian_queue(const uml_model* m, uml_data* d, const double* d_theta, double* h_out,
+                  hipStream_t s, const char* fn) {
+  if (!m || !d || !d_theta || !h_out) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
   if (d->model != m)
     return set_error(UML_E_INVALID, std::string(fn) + ": data was created for another model");
   if (!m->d_hplan)
@@ -51,7 +63,7 @@ int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream
   const int n_tiles = HL.n_tiles;
   const size_t fixed = hess_lds_bytes(row, 0, P.precision);
   const size_t esz = P.precision == UML_MIXED ? 4 : 8;
-  int chunk = 64;
+  int chunk = kBlock;  // events staged at once: as many as LDS allows, up to one per thread
   while (chunk > 1 && fixed + size_t(row) * chunk * esz > 60 * 1024) chunk /= 2;
   if (fixed + size_t(row) * chunk * esz > 64 * 1024)
     return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": model too large for the Hessian pass");
@@ -79,25 +91,34 @@ int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream
   A.hplan = m->d_hplan;
   A.part = reinterpret_cast<double*>(base + o_part);
   A.n_tiles = n_tiles;
-  A.tile_events = kHessTileEvents;
+  A.tile_events = hess_tile_events(d->n);
   A.chunk = chunk;
   A.row_len = row;
   A.n_sums = M;
-  std::memcpy(d->h_stage, theta, sizeof(double) * P.npar);
-  UML_HIP_CHECK(hipMemcpyAsync(d->d_theta, d->h_stage, sizeof(double) * P.npar,
-                               hipMemcpyHostToDevice, s));
-  launch_hessian(A, d->d_theta, reinterpret_cast<ConstBlock*>(base + o_cb),
+  launch_hessian(A, d_theta, reinterpret_cast<ConstBlock*>(base + o_cb),
                  reinterpret_cast<double*>(base + o_hc), reinterpret_cast<double*>(base + o_out),
                  P.precision, s);
   UML_HIP_CHECK(hipGetLastError());
-  out.assign(M, 0.0);
-  UML_HIP_CHECK(hipMemcpyAsync(out.data(), base + o_out, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+  UML_HIP_CHECK(hipMemcpyAsync(h_out, base + o_out, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+  return UML_OK;
+}
+
+// The Hessian pass for a host parameter vector, synchronously.
+int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
+                 std::vector<double>& out, const char* fn) {
+  if (!m || !d || !theta) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+  std::memcpy(d->h_stage, theta, sizeof(double) * m->plan.npar);
+  UML_HIP_CHECK(hipMemcpyAsync(d->d_theta, d->h_stage, sizeof(double) * m->plan.npar,
+                               hipMemcpyHostToDevice, s));
+  out.assign(hess_sums(m), 0.0);
+  int rc = hessian_queue(m, d, d->d_theta, out.data(), s, fn);
+  if (rc != UML_OK) return rc;
   UML_HIP_CHECK(hipStreamSynchronize(s));
   return UML_OK;
 }
 
 // Raw Hessian-pass sums -> NLL, gradient, Hessian, W2 (free parameters).
-int unpack_hessian(const uml_model* m, const std::vector<double>& h, double* nll, double* grad,
+int unpack_hessian(const uml_model* m, const double* h, double* nll, double* grad,
                    double* hess, double* w2, const char* fn) {
   const int nf = m->plan.nfree, np = m->hplan.npairs;
   const double v = -0.69314718055994530942 * h[0];
@@ -150,14 +171,10 @@ bool chol_inverse(int n, const double* A, double* Ai) {
 
 // The start metric: the inverse of the analytic Hessian at the start point
 // (its diagonal inverse if the Hessian is not positive definite there).
-int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V0, double* nll0,
-                 hipStream_t s, const char* fn) {
+int metric_from_sums(const uml_model* m, const double* h, double* V0, double* nll0, const char* fn) {
   const int nf = m->plan.nfree;
-  std::vector<double> h;
-  int rc = hessian_host(m, d, theta, s, h, fn);
-  if (rc != UML_OK) return rc;
   std::vector<double> H(size_t(nf) * nf);
-  rc = unpack_hessian(m, h, nll0, nullptr, H.data(), nullptr, fn);
+  int rc = unpack_hessian(m, h, nll0, nullptr, H.data(), nullptr, fn);
   if (rc != UML_OK) return rc;
   std::vector<double> Vi(size_t(nf) * nf);
   for (int i = 0; i < UML_MAX_PARAMS * UML_MAX_PARAMS; ++i) V0[i] = 0.0;
@@ -175,66 +192,78 @@ int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V
 
 // Final HESSE-like step at the fitted point (and optional Newton polish):
 // covariance = inverse Hessian, errors, EDM with the exact Hessian.
-int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta, int polish,
-               int want_cov, uml_fit_result* r, hipStream_t s, const char* fn) {
+int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta,
+               const uml_fit_options& o, uml_fit_result* r, hipStream_t s, const char* fn) {
   const Plan& P = m->plan;
   const int nf = P.nfree;
   std::vector<double> h, g(nf), H(size_t(nf) * nf), C(size_t(nf) * nf);
-  double nll = 0.0;
-  for (int it = 0; it <= polish; ++it) {
+  for (int it = 0; it < o.polish; ++it) {  // Newton steps with the analytic Hessian
     int rc = hessian_host(m, d, theta.data(), s, h, fn);
     if (rc != UML_OK) return rc;
-    rc = unpack_hessian(m, h, &nll, g.data(), H.data(), nullptr, fn);
-    if (rc != UML_OK) {
-      r->status = UML_FIT_PDF_NONPOSITIVE;
-      return UML_OK;
-    }
-    const bool pd = chol_inverse(nf, H.data(), C.data());
-    if (!pd) {
-      if (r->status == UML_FIT_CONVERGED) r->status = UML_FIT_HESSIAN_NOT_PD;
-      break;
-    }
-    if (it == polish) break;
-    std::vector<double> t2 = theta;  // Newton step with the analytic Hessian
+    if (unpack_hessian(m, h.data(), nullptr, g.data(), H.data(), nullptr, fn) != UML_OK ||
+        !chol_inverse(nf, H.data(), C.data()))
+      break;  // the final pass below reports the state of this point
     for (int a = 0; a < nf; ++a) {
       double st = 0.0;
       for (int b = 0; b < nf; ++b) st -= C[a * nf + b] * g[b];
-      t2[P.free_idx[a]] += st;
+      theta[P.free_idx[a]] += st;
     }
-    theta.swap(t2);
+  }
+  int rc = hessian_host(m, d, theta.data(), s, h, fn);
+  if (rc != UML_OK) return rc;
+  finish_from_sums(m, h.data(), theta.data(), o, r, fn);
+  return UML_OK;
+}
+
+// Result at the fitted point from its Hessian-pass sums: NLL, EDM with the
+// exact Hessian, and the covariance (with the errors its diagonal gives):
+// H^-1, or for weighted fits the sandwich H^-1 W2 H^-1.
+void finish_from_sums(const uml_model* m, const double* h, const double* theta,
+                      const uml_fit_options& o, uml_fit_result* r, const char* fn) {
+  const Plan& P = m->plan;
+  const int nf = P.nfree;
+  std::vector<double> g(nf), H(size_t(nf) * nf), C(size_t(nf) * nf, 0.0), W2(size_t(nf) * nf);
+  double nll = 0.0;
+  for (int k = 0; k < UML_MAX_PARAMS; ++k) r->params[k] = k < P.npar ? theta[k] : 0.0;
+  if (unpack_hessian(m, h, &nll, g.data(), H.data(), W2.data(), fn) != UML_OK) {
+    r->status = UML_FIT_PDF_NONPOSITIVE;
+    r->nll = INFINITY;
+    return;
+  }
+  if (!chol_inverse(nf, H.data(), C.data())) {
+    if (r->status == UML_FIT_CONVERGED) r->status = UML_FIT_HESSIAN_NOT_PD;
+    std::fill(C.begin(), C.end(), 0.0);
   }
   double edm = 0.0;
   for (int a = 0; a < nf; ++a)
     for (int b = 0; b < nf; ++b) edm += 0.5 * g[a] * C[a * nf + b] * g[b];
-  for (int k = 0; k < UML_MAX_PARAMS; ++k) {
-    r->params[k] = k < P.npar ? theta[k] : 0.0;
-    r->errors[k] = 0.0;
+  std::vector<double> V = C;
+  if (o.cov_kind == UML_COV_SANDWICH) {  // V = C W2 C
+    std::vector<double> T(size_t(nf) * nf, 0.0);
+    for (int a = 0; a < nf; ++a)
+      for (int k = 0; k < nf; ++k)
+        for (int b = 0; b < nf; ++b) T[a * nf + b] += C[a * nf + k] * W2[k * nf + b];
+    for (int a = 0; a < nf; ++a)
+      for (int b = 0; b < nf; ++b) {
+        double v = 0.0;
+        for (int k = 0; k < nf; ++k) v += T[a * nf + k] * C[k * nf + b];
+        V[a * nf + b] = v;
+      }
   }
+  for (int k = 0; k < UML_MAX_PARAMS; ++k) r->errors[k] = 0.0;
   for (int a = 0; a < nf; ++a) {
-    r->errors[P.free_idx[a]] = std::sqrt(std::max(C[a * nf + a], 0.0));
-    for (int b = 0; b < nf; ++b) r->cov[a * nf + b] = want_cov ? C[a * nf + b] : 0.0;
+    r->errors[P.free_idx[a]] = std::sqrt(std::max(V[a * nf + a], 0.0));
+    for (int b = 0; b < nf; ++b) r->cov[a * nf + b] = o.want_cov ? V[a * nf + b] : 0.0;
   }
   r->nll = nll;
   r->edm = edm;
-  return UML_OK;
 }
 
-// A fit's device state at its start point (the start metric from the
-// analytic Hessian).  A start with P <= 0 somewhere gives a finished state.
-int init_fit_state(const uml_model* m, uml_data* d, const double* start, const uml_fit_options& o,
-                   FitState& F, hipStream_t s, const char* fn) {
+// The parts of a fit's start state that need no evaluation.
+void fit_state_begin(const uml_model* m, const double* start, const uml_fit_options& o, FitState& F) {
   const Plan& P = m->plan;
   std::memset(&F, 0, sizeof(F));
   for (int k = 0; k < P.npar; ++k) F.theta[k] = start[k];
-  double nll0 = 0.0;
-  int rc = start_metric(m, d, start, F.V0, &nll0, s, fn);
-  if (rc == UML_E_PDF_NONPOSITIVE) {
-    F.done = 1;
-    F.status = UML_FIT_PDF_NONPOSITIVE;
-    return UML_OK;
-  }
-  if (rc != UML_OK) return rc;
-  std::memcpy(F.V, F.V0, sizeof(F.V));
   F.phase = 0;
   F.alpha = 1.0;
   F.edm = INFINITY;
@@ -245,6 +274,117 @@ int init_fit_state(const uml_model* m, uml_data* d, const double* start, const u
   // ln P of every event of a component together by up to ~2^-24 |log2 K|:
   // the NLL steps by a few 1e-8 of itself between nearby points.
   F.tol_f_rel = P.precision == UML_MIXED ? 2e-7 : 1e-14;
+}
+
+// Completes a start state from the Hessian-pass sums at the start point (the
+// start metric).  A start with P <= 0 somewhere gives a finished state.
+int fit_state_metric(const uml_model* m, const double* h, FitState& F, const char* fn) {
+  double nll0 = 0.0;
+  int rc = metric_from_sums(m, h, F.V0, &nll0, fn);
+  if (rc == UML_E_PDF_NONPOSITIVE) {
+    F.done = 1;
+    F.status = UML_FIT_PDF_NONPOSITIVE;
+    return UML_OK;
+  }
+  if (rc != UML_OK) return rc;
+  std::memcpy(F.V, F.V0, sizeof(F.V));
+  return UML_OK;
+}
+
+// A fit's device state at its start point, synchronously.
+int init_fit_state(const uml_model* m, uml_data* d, const double* start, const uml_fit_options& o,
+                   FitState& F, hipStream_t s, const char* fn) {
+  fit_state_begin(m, start, o, F);
+  std::vector<double> h;
+  int rc = hessian_host(m, d, start, s, h, fn);
+  if (rc != UML_OK) return rc;
+  return fit_state_metric(m, h.data(), F, fn);
+}
+
+int check_fit_options(const uml_fit_options& o, const char* fn) {
+  if (!(o.edm_tol > 0.0) || !std::isfinite(o.edm_tol) || o.max_iter < 1 || o.polish < 0 ||
+      o.polish > 16 || (o.cov_kind != UML_COV_HESSE && o.cov_kind != UML_COV_SANDWICH) ||
+      (o.method != UML_METHOD_BFGS && o.method != UML_METHOD_NEWTON))
+    return set_error(UML_E_INVALID, std::string(fn) +
+                                        ": fit options out of range (edm_tol > 0, max_iter >= 1, "
+                                        "0 <= polish <= 16, cov_kind HESSE or SANDWICH, method "
+                                        "BFGS or NEWTON)");
+  return UML_OK;
+}
+
+// Newton iterations with the analytic Hessian: each iteration is one
+// Hessian pass (NLL, gradient, Hessian at the current point) and a Newton
+// step, shortened by backtracking until the Armijo condition holds (event
+// kernel evaluations).  With exact second derivatives the minimisation takes
+// a few iterations (the analytic-derivative fits of Sec. 3.2-3.3).  Where the
+// Hessian is not positive definite the step uses its inverse diagonal.
+// Stops at EDM = 0.5 g^T H^-1 g < edm_tol; the last Hessian pass gives the
+// covariance, so no pass is added at the end.
+static int newton_fit(const uml_model* m, uml_data* d, const double* start, const uml_fit_options& o,
+                      uml_fit_result* r, const char* fn) {
+  const Plan& P = m->plan;
+  const int nf = P.nfree;
+  const double tol_f_rel = P.precision == UML_MIXED ? 2e-7 : 1e-14;
+  std::vector<double> th(start, start + P.npar), tt(P.npar), h, g(nf), H(size_t(nf) * nf),
+      C(size_t(nf) * nf), p(nf);
+  int status = UML_FIT_MAX_ITER, it = 0, n_eval = 0;
+  for (;; ++it) {
+    int rc = hessian_host(m, d, th.data(), nullptr, h, fn);
+    if (rc != UML_OK) return rc;
+    ++n_eval;
+    double f = 0.0;
+    if (unpack_hessian(m, h.data(), &f, g.data(), H.data(), nullptr, fn) != UML_OK) {
+      status = UML_FIT_PDF_NONPOSITIVE;  // only at the start: steps to +inf are rejected
+      break;
+    }
+    const bool pd = chol_inverse(nf, H.data(), C.data());
+    if (!pd) {
+      std::fill(C.begin(), C.end(), 0.0);
+      for (int a = 0; a < nf; ++a) {
+        const double haa = std::fabs(H[a * nf + a]);
+        C[a * nf + a] = haa > 0.0 ? 1.0 / haa : 1.0;
+      }
+    }
+    double gp = 0.0;
+    for (int a = 0; a < nf; ++a) {
+      double pa = 0.0;
+      for (int b = 0; b < nf; ++b) pa -= C[a * nf + b] * g[b];
+      p[a] = pa;
+      gp += g[a] * pa;
+    }
+    const double edm = -0.5 * gp;
+    if (pd && edm < o.edm_tol) {
+      status = UML_FIT_CONVERGED;
+      break;
+    }
+    if (it >= o.max_iter) break;
+    bool accepted = false;
+    double alpha = 1.0;
+    for (int ls = 0; ls < 40 && !accepted; ++ls, alpha *= 0.5) {
+      tt = th;
+      for (int a = 0; a < nf; ++a) tt[P.free_idx[a]] += alpha * p[a];
+      double ft = 0.0;
+      rc = uml_eval_nll(m, d, tt.data(), &ft, nullptr);
+      ++n_eval;
+      if (rc != UML_OK && rc != UML_E_PDF_NONPOSITIVE) return rc;
+      accepted = rc == UML_OK && ft <= f + 1e-4 * alpha * gp + tol_f_rel * std::fabs(f);
+    }
+    if (!accepted) {
+      status = edm < 100.0 * o.edm_tol ? UML_FIT_CONVERGED : UML_FIT_LINESEARCH_FAIL;
+      break;
+    }
+    th.swap(tt);
+  }
+  r->n_free = nf;
+  r->n_iter = it;
+  r->n_eval = n_eval;
+  r->status = status;
+  if (status == UML_FIT_PDF_NONPOSITIVE) {
+    for (int k = 0; k < UML_MAX_PARAMS; ++k) r->params[k] = k < P.npar ? th[k] : 0.0;
+    r->nll = INFINITY;
+    return UML_OK;
+  }
+  finish_from_sums(m, h.data(), th.data(), o, r, fn);  // h is the pass at th
   return UML_OK;
 }
 
@@ -253,6 +393,7 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
   uml_fit_options o;
   uml_fit_options_default(&o);
   if (opts) o = *opts;
+  if (int rc = check_fit_options(o, fn)) return rc;
   if (n == 0) return UML_OK;
   const Plan& P = m->plan;
   for (int i = 0; i < n; ++i) {
@@ -262,6 +403,14 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
     for (int j = 0; j < i; ++j)
       if (ds[j] == ds[i])
         return set_error(UML_E_INVALID, std::string(fn) + ": the same data handle appears twice");
+  }
+  if (o.method == UML_METHOD_NEWTON) {
+    for (int i = 0; i < n; ++i) {
+      std::memset(&out[i], 0, sizeof(uml_fit_result));
+      int rc = newton_fit(m, const_cast<uml_data*>(ds[i]), starts + size_t(i) * P.npar, o, &out[i], fn);
+      if (rc != UML_OK) return rc;
+    }
+    return UML_OK;
   }
   std::vector<FitState> fs(n);
   std::vector<int> live;
@@ -279,14 +428,18 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
   const size_t o_fs = 0, o_job = (sizeof(FitState) * n + 255) / 256 * 256;
   const size_t o_map = o_job + (sizeof(Job) * n + 255) / 256 * 256;
   const size_t bytes = o_map + sizeof(int2) * std::max(total_tiles, 1);
-  void* dmem = nullptr;
-  hipError_t e = hipMalloc(&dmem, bytes);
-  if (e != hipSuccess) return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
-  struct Free {
-    void* p;
-    ~Free() { if (p) (void)hipFree(p); }
-  } guard{dmem};
-  char* base = static_cast<char*>(dmem);
+  if (m->fitws_bytes < bytes) {  // the model's fit workspace, grown on demand
+    if (m->d_fitws) (void)hipFree(m->d_fitws);
+    m->d_fitws = nullptr;
+    m->fitws_bytes = 0;
+    hipError_t e = hipMalloc(&m->d_fitws, bytes);
+    if (e != hipSuccess) {
+      m->d_fitws = nullptr;
+      return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
+    }
+    m->fitws_bytes = bytes;
+  }
+  char* base = static_cast<char*>(m->d_fitws);
   FitState* d_fs = reinterpret_cast<FitState*>(base + o_fs);
   Job* d_jobs = reinterpret_cast<Job*>(base + o_job);
   int2* d_map = reinterpret_cast<int2*>(base + o_map);
@@ -358,7 +511,7 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
       r.nll = INFINITY;
       continue;
     }
-    int rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o.polish, o.want_cov, &r, nullptr, fn);
+    int rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o, &r, nullptr, fn);
     if (rc != UML_OK) return rc;
   }
   return UML_OK;
@@ -374,6 +527,8 @@ void uml_fit_options_default(uml_fit_options* o) {
   o->max_iter = 1000;
   o->polish = 0;
   o->want_cov = 1;
+  o->cov_kind = UML_COV_HESSE;
+  o->method = UML_METHOD_BFGS;
 }
 
 int uml_eval_hessian(const uml_model* m, const uml_data* d, const double* theta_all, double* nll,
@@ -382,7 +537,7 @@ int uml_eval_hessian(const uml_model* m, const uml_data* d, const double* theta_
   int rc = hessian_host(m, const_cast<uml_data*>(d), theta_all, static_cast<hipStream_t>(stream), h,
                         "uml_eval_hessian");
   if (rc != UML_OK) return rc;
-  return unpack_hessian(m, h, nll, grad_free, hess_free, w2_free, "uml_eval_hessian");
+  return unpack_hessian(m, h.data(), nll, grad_free, hess_free, w2_free, "uml_eval_hessian");
 }
 
 int uml_fit(const uml_model* m, const uml_data* d, const double* start_all,

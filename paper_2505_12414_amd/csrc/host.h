@@ -19,6 +19,10 @@ struct uml_model {
   uml::HessPlan hplan;
   uml::HessPlan* d_hplan = nullptr;  // device copy (nullptr: no Hessian, see hess_err)
   std::string hess_err;
+  // device workspace of uml_fit / uml_fit_batch (fit states, jobs, tile map),
+  // grown on demand and kept until the model is destroyed
+  mutable void* d_fitws = nullptr;
+  mutable size_t fitws_bytes = 0;
 };
 
 struct uml_data {
@@ -35,7 +39,8 @@ struct uml_data {
   double* d_out = nullptr;          // [1 + nfree]
   void* d_hwork = nullptr;          // Hessian workspace (allocated on first use)
   int hess_tiles = 0;
-  double* h_stage = nullptr;        // pinned host staging
+  double* h_stage = nullptr;        // pinned host staging (a block of the process pool)
+  void* d_alloc = nullptr;          // the device allocation this dataset owns
   int64_t bytes_events = 0;
   int64_t bytes_work = 0;
   int owns_memory = 0;              // 0: memory belongs to a server's arena
@@ -64,18 +69,27 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
                void* d_events, void* d_work);
 hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s);
 size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles);
+double* pinned_stage_get();
+void pinned_stage_put(double* p);
 
+int hess_sums(const uml_model* m);
+int hessian_queue(const uml_model* m, uml_data* d, const double* d_theta, double* h_out,
+                  hipStream_t s, const char* fn);
 int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
                  std::vector<double>& out, const char* fn);
-int unpack_hessian(const uml_model* m, const std::vector<double>& h, double* nll, double* grad,
-                   double* hess, double* w2, const char* fn);
+int unpack_hessian(const uml_model* m, const double* h, double* nll, double* grad, double* hess,
+                   double* w2, const char* fn);
 bool chol_inverse(int n, const double* A, double* Ai);
-int start_metric(const uml_model* m, uml_data* d, const double* theta, double* V0, double* nll0,
-                 hipStream_t s, const char* fn);
-int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta, int polish,
-               int want_cov, uml_fit_result* r, hipStream_t s, const char* fn);
+int metric_from_sums(const uml_model* m, const double* h, double* V0, double* nll0, const char* fn);
+void finish_from_sums(const uml_model* m, const double* h, const double* theta,
+                      const uml_fit_options& o, uml_fit_result* r, const char* fn);
+int finish_fit(const uml_model* m, uml_data* d, std::vector<double>& theta,
+               const uml_fit_options& o, uml_fit_result* r, hipStream_t s, const char* fn);
 int init_fit_state(const uml_model* m, uml_data* d, const double* start, const uml_fit_options& o,
                    FitState& F, hipStream_t s, const char* fn);
+void fit_state_begin(const uml_model* m, const double* start, const uml_fit_options& o, FitState& F);
+int fit_state_metric(const uml_model* m, const double* h, FitState& F, const char* fn);
+int check_fit_options(const uml_fit_options& o, const char* fn);
 int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const double* starts,
                    const uml_fit_options* opts, uml_fit_result* out, const char* fn);
 

@@ -106,7 +106,31 @@ struct Slot {
   size_t o_work = 0, o_hess = 0;
 };
 
+// Pinned host staging of one slot: the start point going up, the fit state
+// and the Hessian-pass sums coming down.  Pinned, so that the copies of a
+// whole batch of slots are queued together and waited for once.
+struct SlotHost {
+  FitState fs;
+  double theta[UML_MAX_PARAMS];
+  double sums[1 + UML_MAX_PARAMS + UML_MAX_PARAMS * (UML_MAX_PARAMS + 1)];
+};
+
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Grid sizes the batched iteration is captured for: the active fits' tiles,
+// rounded up to the next size of a geometric ladder (ratio about 1.19), so a
+// changing active set reuses a few captured graphs; the padding tiles exit
+// at once.
+int grid_bucket(int grid) {
+  int b = 64;
+  while (b < grid) b = std::max(b + 64, int(double(b) * 1.1892));
+  return b;
+}
+
+struct CapturedGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 }  // namespace
 
@@ -122,7 +146,8 @@ struct uml_server {
   std::deque<Request> pending;
   std::deque<uml_fit_result> results;
   uint64_t next_ticket = 1;
-  int64_t submitted = 0, admitted = 0, finished = 0, iterations = 0, resident = 0;
+  int64_t submitted = 0, admitted = 0, finished = 0, iterations = 0;
+  int64_t resident = 0, peak_resident = 0, budget_waits = 0;  // arena bytes in use
   int active = 0;
   bool stop = false;
   int worker_error = 0;
@@ -137,12 +162,11 @@ struct uml_server {
   Job* d_jobs = nullptr;
   int2* d_map = nullptr;
   int map_cap = 0;
-  double* h_stage = nullptr;
+  SlotHost* h_slots = nullptr;  // pinned, one per slot
+  int* h_done = nullptr;        // pinned, one per slot
   std::vector<Slot> slots;
   std::vector<Job> jobs;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  int graph_grid = -1;
+  std::map<int, CapturedGraph> graphs;  // by grid bucket
 };
 
 namespace uml {
@@ -174,105 +198,178 @@ void push_result(uml_server* S, uml_fit_result& r, const Request& q) {
   S->cv_result.notify_all();
 }
 
-// Places an admitted request in slot i: arena memory, upload, start metric.
-// Returns false (after queueing its result) when the fit is finished at once.
-int admit(uml_server* S, int i, size_t off, Request&& q, bool* started) {
+void release_slot(uml_server* S, Slot& sl) {
+  S->arena.release(sl.off, sl.req.bytes);
+  sl.used = false;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->resident -= int64_t(sl.req.bytes);
+}
+
+struct Intake {
+  int slot;
+  size_t off;
+  Request req;
+};
+
+// Admits a batch of requests: places each in its slot's arena memory,
+// uploads its events, queues the Hessian pass at its start point (the start
+// metric), waits once for the whole batch, then writes the fit states.  A
+// request whose start point has P <= 0 somewhere is answered at once.
+int admit_batch(uml_server* S, std::vector<Intake>& in) {
   const uml_model* m = S->m;
-  Slot& sl = S->slots[i];
-  *started = false;
-  sl.off = off;
-  sl.used = true;
-  sl.req = std::move(q);
-  sl.layout = data_layout(m->plan, sl.req.n, sl.req.weighted);
-  sl.o_work = round256(sl.layout.bytes_events);
-  sl.o_hess = sl.o_work + round256(sl.layout.bytes_work);
-  sl.data = uml_data();
-  data_bind(&sl.data, m, sl.req.n, sl.req.weighted, sl.layout, S->arena.at(sl.off),
-            S->arena.at(sl.off + sl.o_work));
-  sl.data.d_hwork = S->arena.at(sl.off + sl.o_hess);
-  hess_work_bytes(m, sl.req.n, &sl.data.hess_tiles);
-  sl.data.h_stage = S->h_stage;
-  sl.data.owns_memory = 0;
-  hipError_t e = data_upload(&sl.data, sl.layout, sl.req.host, S->stream);
-  if (e != hipSuccess) return set_error(UML_E_HIP, std::string("server upload: ") + hipGetErrorString(e));
-  std::vector<char>().swap(sl.req.host);  // the host copy is no longer needed
-  FitState F;
-  int rc = init_fit_state(m, &sl.data, sl.req.start.data(), S->opt.fit, F, S->stream, "server");
-  if (rc != UML_OK) return rc;
-  if (F.done) {  // P <= 0 at the start point
-    uml_fit_result r;
-    std::memset(&r, 0, sizeof(r));
-    r.n_free = m->plan.nfree;
-    r.status = F.status;
-    r.nll = INFINITY;
-    for (int k = 0; k < m->plan.npar; ++k) r.params[k] = sl.req.start[k];
-    push_result(S, r, sl.req);
-    S->arena.release(sl.off, sl.req.bytes);
-    sl.used = false;
-    return UML_OK;
+  for (auto& it : in) {
+    Slot& sl = S->slots[it.slot];
+    sl.off = it.off;
+    sl.used = true;
+    sl.req = std::move(it.req);
+    sl.layout = data_layout(m->plan, sl.req.n, sl.req.weighted);
+    sl.o_work = round256(sl.layout.bytes_events);
+    sl.o_hess = sl.o_work + round256(sl.layout.bytes_work);
+    sl.data = uml_data();
+    data_bind(&sl.data, m, sl.req.n, sl.req.weighted, sl.layout, S->arena.at(sl.off),
+              S->arena.at(sl.off + sl.o_work));
+    sl.data.d_hwork = S->arena.at(sl.off + sl.o_hess);
+    hess_work_bytes(m, sl.req.n, &sl.data.hess_tiles);
+    sl.data.h_stage = S->h_slots[it.slot].theta;
+    sl.data.owns_memory = 0;
+    hipError_t e = data_upload(&sl.data, sl.layout, sl.req.host, S->stream);
+    if (e != hipSuccess) return set_error(UML_E_HIP, std::string("server upload: ") + hipGetErrorString(e));
+    SlotHost& H = S->h_slots[it.slot];
+    std::memcpy(H.theta, sl.req.start.data(), sizeof(double) * m->plan.npar);
+    UML_HIP_CHECK(hipMemcpyAsync(sl.data.d_theta, H.theta, sizeof(double) * m->plan.npar,
+                                 hipMemcpyHostToDevice, S->stream));
+    int rc = hessian_queue(m, &sl.data, sl.data.d_theta, H.sums, S->stream, "server");
+    if (rc != UML_OK) return rc;
   }
-  Job J = sl.data.job;
-  J.fit = S->d_fs + i;
-  J.theta = S->d_fs[i].theta;
-  J.out = S->d_fs[i].out;
-  S->jobs[i] = J;
-  UML_HIP_CHECK(hipMemcpyAsync(S->d_fs + i, &F, sizeof(FitState), hipMemcpyHostToDevice, S->stream));
-  UML_HIP_CHECK(hipMemcpyAsync(S->d_jobs + i, &J, sizeof(Job), hipMemcpyHostToDevice, S->stream));
-  *started = true;
+  UML_HIP_CHECK(hipStreamSynchronize(S->stream));
+  for (auto& it : in) {
+    const int i = it.slot;
+    Slot& sl = S->slots[i];
+    SlotHost& H = S->h_slots[i];
+    std::vector<char>().swap(sl.req.host);  // uploaded
+    fit_state_begin(m, sl.req.start.data(), S->opt.fit, H.fs);
+    int rc = fit_state_metric(m, H.sums, H.fs, "server");
+    if (rc != UML_OK) return rc;
+    if (H.fs.done) {  // P <= 0 at the start point
+      uml_fit_result r;
+      std::memset(&r, 0, sizeof(r));
+      r.n_free = m->plan.nfree;
+      r.status = H.fs.status;
+      r.nll = INFINITY;
+      for (int k = 0; k < m->plan.npar; ++k) r.params[k] = sl.req.start[k];
+      release_slot(S, sl);
+      push_result(S, r, sl.req);
+      continue;
+    }
+    Job J = sl.data.job;
+    J.fit = S->d_fs + i;
+    J.theta = S->d_fs[i].theta;
+    J.out = S->d_fs[i].out;
+    S->jobs[i] = J;
+    UML_HIP_CHECK(hipMemcpyAsync(S->d_fs + i, &H.fs, sizeof(FitState), hipMemcpyHostToDevice, S->stream));
+    UML_HIP_CHECK(hipMemcpyAsync(S->d_jobs + i, &S->jobs[i], sizeof(Job), hipMemcpyHostToDevice, S->stream));
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->active++;
+  }
   return UML_OK;
 }
 
-// Retires slot i: final Hessian at the fitted point, result, memory.
-int retire(uml_server* S, int i) {
+// Retires a batch of finished fits: queues, for each, the copy of its fit
+// state and the Hessian pass at its final point (read on the device), waits
+// once, then forms the results (covariance from the inverse Hessian) and
+// frees the slots.  Newton polishing, when asked for, runs fit by fit.
+int retire_batch(uml_server* S, const std::vector<int>& fin) {
   const uml_model* m = S->m;
   const Plan& P = m->plan;
-  Slot& sl = S->slots[i];
-  FitState F;
-  UML_HIP_CHECK(hipMemcpyAsync(&F, S->d_fs + i, sizeof(FitState), hipMemcpyDeviceToHost, S->stream));
-  UML_HIP_CHECK(hipStreamSynchronize(S->stream));
-  uml_fit_result r;
-  std::memset(&r, 0, sizeof(r));
-  r.n_free = P.nfree;
-  r.n_iter = F.n_iter;
-  r.n_eval = F.n_eval;
-  r.status = F.status;
-  std::vector<double> theta(F.theta, F.theta + P.npar);
-  if (r.status == UML_FIT_PDF_NONPOSITIVE) {
-    for (int k = 0; k < P.npar; ++k) r.params[k] = theta[k];
-    r.nll = INFINITY;
-  } else {
-    int rc = finish_fit(m, &sl.data, theta, S->opt.fit.polish, S->opt.fit.want_cov, &r, S->stream,
-                        "server");
-    if (rc != UML_OK) return rc;
+  const bool polish = S->opt.fit.polish > 0;
+  for (int i : fin) {
+    SlotHost& H = S->h_slots[i];
+    UML_HIP_CHECK(hipMemcpyAsync(&H.fs, S->d_fs + i, sizeof(FitState), hipMemcpyDeviceToHost, S->stream));
+    if (!polish) {
+      int rc = hessian_queue(m, &S->slots[i].data, S->d_fs[i].theta, H.sums, S->stream, "server");
+      if (rc != UML_OK) return rc;
+    }
   }
-  push_result(S, r, sl.req);
-  S->arena.release(sl.off, sl.req.bytes);
-  sl.used = false;
+  UML_HIP_CHECK(hipStreamSynchronize(S->stream));
+  for (int i : fin) {
+    Slot& sl = S->slots[i];
+    const FitState& F = S->h_slots[i].fs;
+    uml_fit_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.n_free = P.nfree;
+    r.n_iter = F.n_iter;
+    r.n_eval = F.n_eval;
+    r.status = F.status;
+    if (r.status == UML_FIT_PDF_NONPOSITIVE) {
+      for (int k = 0; k < P.npar; ++k) r.params[k] = F.theta[k];
+      r.nll = INFINITY;
+    } else if (!polish) {
+      finish_from_sums(m, S->h_slots[i].sums, F.theta, S->opt.fit, &r, "server");
+    } else {
+      std::vector<double> theta(F.theta, F.theta + P.npar);
+      int rc = finish_fit(m, &sl.data, theta, S->opt.fit, &r, S->stream, "server");
+      if (rc != UML_OK) return rc;
+    }
+    release_slot(S, sl);
+    push_result(S, r, sl.req);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->active--;
+  }
+  return UML_OK;
+}
+
+// The captured batched iteration for a grid bucket (captured on first use).
+int graph_for(uml_server* S, int bucket, hipGraphExec_t* exec) {
+  auto it = S->graphs.find(bucket);
+  if (it != S->graphs.end()) {
+    *exec = it->second.exec;
+    return UML_OK;
+  }
+  const uml_model* m = S->m;
+  LaunchArgs a{};
+  a.job0 = S->jobs[0];
+  a.jobs = S->d_jobs;
+  a.tmap = S->d_map;
+  a.grid = bucket;
+  a.precision = m->plan.precision;
+  a.stream = S->stream;
+  CapturedGraph g;
+  hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+  for (int k = 0; k < kItersPerReplay && e == hipSuccess; ++k) m->family->eval(a);
+  if (e == hipSuccess) e = hipStreamEndCapture(S->stream, &g.graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    return set_error(UML_E_HIP, std::string("server graph: ") + hipGetErrorString(e));
+  }
+  S->graphs[bucket] = g;
+  *exec = g.exec;
   return UML_OK;
 }
 
 void worker_main(uml_server* S) {
   (void)hipSetDevice(S->m->device);
-  const uml_model* m = S->m;
+  const int ns = int(S->slots.size());
   std::vector<int2> map;
-  std::vector<int> done(S->slots.size(), 0);
+  std::vector<int> fin;
   bool dirty = true;
+  int bucket = 0;
   while (true) {
-    struct Intake {
-      int slot;
-      size_t off;
-      Request req;
-    };
     std::vector<Intake> intake;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (S->stop && S->pending.empty() && S->active == 0) break;
       // admission, in arrival order: a free slot and room in the arena (the
       // memory budget); the arena belongs to this thread
-      for (int i = 0; i < int(S->slots.size()) && !S->pending.empty(); ++i) {
+      for (int i = 0; i < ns && !S->pending.empty(); ++i) {
         if (S->slots[i].used) continue;
         size_t off = 0;
-        if (!S->arena.alloc(S->pending.front().bytes, &off)) break;
+        if (!S->arena.alloc(S->pending.front().bytes, &off)) {
+          S->budget_waits++;
+          break;
+        }
+        S->resident += int64_t(S->pending.front().bytes);
+        S->peak_resident = std::max(S->peak_resident, S->resident);
         intake.push_back({i, off, std::move(S->pending.front())});
         S->pending.pop_front();
       }
@@ -282,31 +379,26 @@ void worker_main(uml_server* S) {
       }
       S->admitted += int64_t(intake.size());
     }
-    for (auto& in : intake) {
-      bool started = false;
-      const int64_t nb = int64_t(in.req.bytes);
-      int rc = admit(S, in.slot, in.off, std::move(in.req), &started);
+    if (!intake.empty()) {
+      int rc = admit_batch(S, intake);
       if (rc != UML_OK) {
         fail_worker(S, rc, uml_last_error());
         return;
       }
-      std::lock_guard<std::mutex> lk(S->mu);
-      if (started) {
-        S->active++;
-        S->resident += nb;
-      }
       dirty = true;
     }
     if (S->active == 0) continue;
-    if (dirty) {  // ragged tile map over the active fits
+    if (dirty) {  // ragged tile map over the active fits, padded to its grid bucket
       map.clear();
-      for (int i = 0; i < int(S->slots.size()); ++i)
+      for (int i = 0; i < ns; ++i)
         if (S->slots[i].used)
           for (int t = 0; t < S->slots[i].data.n_tiles; ++t) map.push_back(make_int2(i, t));
-      if (int(map.size()) > S->map_cap) {
+      bucket = grid_bucket(int(map.size()));
+      if (bucket > S->map_cap) {
         fail_worker(S, UML_E_INVALID, "server: tile map capacity exceeded");
         return;
       }
+      map.resize(bucket, make_int2(-1, -1));
       hipError_t e = hipMemcpyAsync(S->d_map, map.data(), sizeof(int2) * map.size(),
                                     hipMemcpyHostToDevice, S->stream);
       if (e != hipSuccess) {
@@ -315,33 +407,16 @@ void worker_main(uml_server* S) {
       }
       dirty = false;
     }
-    const int grid = int(map.size());
-    if (grid != S->graph_grid) {  // capture kItersPerReplay iterations for this grid
-      if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
-      if (S->graph) (void)hipGraphDestroy(S->graph);
-      S->gexec = nullptr;
-      S->graph = nullptr;
-      LaunchArgs a{};
-      a.job0 = S->jobs[0];
-      a.jobs = S->d_jobs;
-      a.tmap = S->d_map;
-      a.grid = grid;
-      a.precision = m->plan.precision;
-      a.stream = S->stream;
-      hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
-      for (int k = 0; k < kItersPerReplay && e == hipSuccess; ++k) m->family->eval(a);
-      if (e == hipSuccess) e = hipStreamEndCapture(S->stream, &S->graph);
-      if (e == hipSuccess) e = hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) {
-        fail_worker(S, UML_E_HIP, std::string("server graph: ") + hipGetErrorString(e));
-        return;
-      }
-      S->graph_grid = grid;
+    hipGraphExec_t exec = nullptr;
+    int rc = graph_for(S, bucket, &exec);
+    if (rc != UML_OK) {
+      fail_worker(S, rc, uml_last_error());
+      return;
     }
-    hipError_t e = hipGraphLaunch(S->gexec, S->stream);
+    hipError_t e = hipGraphLaunch(exec, S->stream);
     if (e == hipSuccess)
-      e = hipMemcpy2DAsync(done.data(), sizeof(int), &S->d_fs[0].done, sizeof(FitState), sizeof(int),
-                           S->slots.size(), hipMemcpyDeviceToHost, S->stream);
+      e = hipMemcpy2DAsync(S->h_done, sizeof(int), &S->d_fs[0].done, sizeof(FitState), sizeof(int), ns,
+                           hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) {
       fail_worker(S, UML_E_HIP, std::string("server iteration: ") + hipGetErrorString(e));
@@ -351,17 +426,15 @@ void worker_main(uml_server* S) {
       std::lock_guard<std::mutex> lk(S->mu);
       S->iterations += kItersPerReplay;
     }
-    for (int i = 0; i < int(S->slots.size()); ++i) {
-      if (!S->slots[i].used || !done[i]) continue;
-      const int64_t nb = int64_t(S->slots[i].req.bytes);
-      int rc = retire(S, i);
+    fin.clear();
+    for (int i = 0; i < ns; ++i)
+      if (S->slots[i].used && S->h_done[i]) fin.push_back(i);
+    if (!fin.empty()) {
+      rc = retire_batch(S, fin);
       if (rc != UML_OK) {
         fail_worker(S, rc, uml_last_error());
         return;
       }
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->active--;
-      S->resident -= nb;
       dirty = true;
     }
   }
@@ -391,17 +464,27 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (S->opt.max_slots <= 0) S->opt.max_slots = 256;
   if (S->opt.hbm_budget <= 0) S->opt.hbm_budget = int64_t(4) << 30;
   if (S->opt.max_pending <= 0) S->opt.max_pending = 1 << 20;
+  if (int rc = check_fit_options(S->opt.fit, "uml_server_create")) {
+    delete S;
+    return rc;
+  }
+  if (S->opt.fit.method != UML_METHOD_BFGS) {
+    delete S;
+    return set_error(UML_E_UNSUPPORTED, "uml_server_create: the server runs device BFGS fits only");
+  }
   const int ns = S->opt.max_slots;
   S->slots.resize(ns);
   S->jobs.resize(ns);
   // tile map capacity: the arena holds at most budget / (bytes of one tile)
   const DataLayout one = data_layout(m->plan, 1, false);
   const int64_t tile_bytes = int64_t(one.E) * kBlock * (m->plan.precision == UML_MIXED ? 4 : 8);
-  S->map_cap = int(std::min<int64_t>(S->opt.hbm_budget / std::max<int64_t>(tile_bytes, 1) + ns, 1 << 22));
+  S->map_cap = grid_bucket(
+      int(std::min<int64_t>(S->opt.hbm_budget / std::max<int64_t>(tile_bytes, 1) + ns, 1 << 22)));
   auto fail = [&](hipError_t e, const char* what) {
     if (S->arena_mem) (void)hipFree(S->arena_mem);
     if (S->state_mem) (void)hipFree(S->state_mem);
-    if (S->h_stage) (void)hipHostFree(S->h_stage);
+    if (S->h_slots) (void)hipHostFree(S->h_slots);
+    if (S->h_done) (void)hipHostFree(S->h_done);
     if (S->stream) (void)hipStreamDestroy(S->stream);
     delete S;
     return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
@@ -417,8 +500,9 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (e != hipSuccess) return fail(e, "fit states");
   e = hipMemset(S->state_mem, 0, o_map);
   if (e != hipSuccess) return fail(e, "fit states");
-  e = hipHostMalloc(reinterpret_cast<void**>(&S->h_stage), sizeof(double) * 4 * (UML_MAX_PARAMS + 2),
-                    hipHostMallocDefault);
+  e = hipHostMalloc(reinterpret_cast<void**>(&S->h_slots), sizeof(SlotHost) * ns, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_done), sizeof(int) * ns, hipHostMallocDefault);
   if (e != hipSuccess) return fail(e, "pinned staging");
   S->arena.init(static_cast<char*>(S->arena_mem), size_t(S->opt.hbm_budget));
   S->d_fs = reinterpret_cast<FitState*>(S->state_mem);
@@ -496,6 +580,8 @@ int uml_server_stats_get(uml_server* S, uml_server_stats* st) {
   st->active = S->active;
   st->iterations = S->iterations;
   st->resident_bytes = S->resident;
+  st->peak_resident_bytes = S->peak_resident;
+  st->budget_waits = S->budget_waits;
   return UML_OK;
 }
 
@@ -517,11 +603,14 @@ void uml_server_destroy(uml_server* S) {
   }
   if (S->worker.joinable()) S->worker.join();
   if (S->stream) (void)hipStreamSynchronize(S->stream);
-  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
-  if (S->graph) (void)hipGraphDestroy(S->graph);
+  for (auto& kv : S->graphs) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipGraphDestroy(kv.second.graph);
+  }
   if (S->arena_mem) (void)hipFree(S->arena_mem);
   if (S->state_mem) (void)hipFree(S->state_mem);
-  if (S->h_stage) (void)hipHostFree(S->h_stage);
+  if (S->h_slots) (void)hipHostFree(S->h_slots);
+  if (S->h_done) (void)hipHostFree(S->h_done);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   delete S;
 }

@@ -73,7 +73,7 @@ class uml_model_desc(C.Structure):
 
 class uml_fit_options(C.Structure):
     _fields_ = [("edm_tol", C.c_double), ("max_iter", C.c_int32), ("polish", C.c_int32),
-                ("want_cov", C.c_int32)]
+                ("want_cov", C.c_int32), ("cov_kind", C.c_int32), ("method", C.c_int32)]
 
 
 class uml_fit_result(C.Structure):
@@ -97,7 +97,8 @@ class uml_request(C.Structure):
 class uml_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("finished", C.c_int64),
                 ("pending", C.c_int64), ("active", C.c_int64), ("iterations", C.c_int64),
-                ("resident_bytes", C.c_int64)]
+                ("resident_bytes", C.c_int64), ("peak_resident_bytes", C.c_int64),
+                ("budget_waits", C.c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -268,7 +269,8 @@ class Data:
                 ev = ev.reshape(1, -1)
             if ev.dtype not in (np.float32, np.float64):
                 ev = ev.astype(np.float64)
-            ev = np.ascontiguousarray(ev)
+            if ev.shape[1] > 1 and ev.strides[1] != ev.itemsize:
+                ev = np.ascontiguousarray(ev)
             dtype = UML_F32 if ev.dtype == np.float32 else UML_F64
             n = ev.shape[1]
             cols = (C.c_void_p * ev.shape[0])(*[ev[d].ctypes.data for d in range(ev.shape[0])])
@@ -289,10 +291,13 @@ class Data:
         self.n = n
         self.weighted = weights is not None
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.uml_data_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 def _theta(model, theta):
@@ -348,10 +353,16 @@ def uml_eval_hessian(model, data, theta=None, want_w2=False, stream=None, allow_
     return res + ((w2[:nf * nf].reshape(nf, nf).copy(),) if want_w2 else ())
 
 
-def fit_options(edm_tol=1e-6, max_iter=1000, polish=0, want_cov=1):
+UML_COV_HESSE, UML_COV_SANDWICH = 0, 1
+UML_METHOD_BFGS, UML_METHOD_NEWTON = 0, 1
+
+
+def fit_options(edm_tol=1e-6, max_iter=1000, polish=0, want_cov=1, cov_kind=UML_COV_HESSE,
+                method=UML_METHOD_BFGS):
     o = uml_fit_options()
     lib().uml_fit_options_default(C.byref(o))
     o.edm_tol, o.max_iter, o.polish, o.want_cov = edm_tol, max_iter, polish, want_cov
+    o.cov_kind, o.method = cov_kind, method
     return o
 
 
@@ -401,15 +412,17 @@ class Server:
         check(lib().uml_server_create(model.handle, C.byref(o), C.byref(h)))
         self.handle = h
         self.model = model
+        self._buf = (uml_fit_result * 256)()   # reused by poll
 
     def submit(self, events, weights=None, start=None):
         """events: (n_dims, n) float32/float64 host array.  Returns the ticket."""
-        ev = np.ascontiguousarray(np.asarray(events))
+        ev = np.asarray(events)
         if ev.ndim == 1:
             ev = ev.reshape(1, -1)
         if ev.dtype not in (np.float32, np.float64):
             ev = ev.astype(np.float64)
-            ev = np.ascontiguousarray(ev)
+        if ev.shape[1] > 1 and ev.strides[1] != ev.itemsize:
+            ev = np.ascontiguousarray(ev)   # rows must be contiguous; views of rows are not copied
         cols = (C.c_void_p * ev.shape[0])(*[ev[d].ctypes.data for d in range(ev.shape[0])])
         wt = None
         if weights is not None:
@@ -421,10 +434,12 @@ class Server:
         check(lib().uml_server_submit(self.handle, C.byref(q), C.byref(t)))
         return t.value
 
-    def poll(self, max_results=1024, timeout_us=0):
-        rs = (uml_fit_result * max_results)()
+    def poll(self, max_results=256, timeout_us=0):
+        """Up to max_results finished fits (at most 256 per call)."""
+        rs = self._buf
+        k = max(1, min(int(max_results), len(rs)))
         n = C.c_int32()
-        rc = lib().uml_server_poll(self.handle, rs, max_results, C.byref(n), timeout_us)
+        rc = lib().uml_server_poll(self.handle, rs, k, C.byref(n), timeout_us)
         check(rc, allow=(UML_E_TIMEOUT,))
         return [result_dict(self.model, rs[i]) for i in range(n.value)]
 

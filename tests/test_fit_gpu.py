@@ -72,6 +72,80 @@ def test_4d_fit_matches_oracle(precision):
                  1e-8 if precision == "fp64" else 1e-4, f"4d-{precision}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_weighted_fit_sandwich_covariance(precision):
+    """Weighted 4-D fit with the sandwich covariance H^-1 W2 H^-1: errors and
+    matrix against the oracle's H and W2 at the fitted point."""
+    desc = W.angmass4d()
+    dtype = np.float32 if precision == "mixed" else np.float64
+    n = 40_000
+    x = rng_events(desc, n, 313, dtype)
+    w = np.random.default_rng(314).uniform(0.5, 1.5, n).astype(dtype)
+    um = uml.Model(desc, precision)
+    ud = uml.Data(um, x, weights=w)
+    say(f"case weighted sandwich fit precision={precision}")
+    r = uml.uml_fit(um, ud, um.theta0, edm_tol=1e-10 if precision == "fp64" else 1e-8,
+                    cov_kind=uml.UML_COV_SANDWICH)
+    assert r["status"] == 0, r["status_name"]
+    rh = uml.uml_fit(um, ud, um.theta0, edm_tol=1e-10 if precision == "fp64" else 1e-8)
+    assert np.array_equal(r["theta"], rh["theta"])   # the covariance choice does not move the fit
+    om = oracle.Model(desc)
+    f = om.free
+    x64, w64 = x.astype(np.float64), w.astype(np.float64)
+    _, _, h, _ = om.nll(x64, r["theta"], w=w64, order=2)
+    w2, bad = om.w2(x64, r["theta"], w64)
+    assert bad == 0
+    C = np.linalg.inv(h[np.ix_(f, f)])
+    V = C @ w2[np.ix_(f, f)] @ C
+    s_or = np.sqrt(np.diag(V))
+    rel = np.abs(r["errors"][f] - s_or) / s_or
+    tol = 1e-8 if precision == "fp64" else 1e-3
+    say(f"  max |dsigma|/sigma {rel.max():.2e}; sandwich/HESSE error ratios "
+        f"{np.round(r['errors'][f] / rh['errors'][f], 3).tolist()}")
+    assert rel.max() <= tol
+    assert np.max(np.abs(r["cov"] - V) / np.outer(s_or, s_or)) <= tol
+    # w ~ U(0.5, 1.5): E[w] = 1, E[w^2] = 13/12, so the sandwich errors exceed
+    # the inverse-Hessian ones by about sqrt(13/12) = 1.04
+    ratio = r["errors"][f] / rh["errors"][f]
+    assert np.all((ratio > 1.0) & (ratio < 1.1)), ratio
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_newton_fit_matches_oracle(precision):
+    """Newton iterations with the analytic Hessian: the same minimum as the
+    oracle's fit, reached in a few iterations."""
+    desc = W.angmass4d()
+    dtype = np.float32 if precision == "mixed" else np.float64
+    x = rng_events(desc, 60_000, 77, dtype)
+    um = uml.Model(desc, precision)
+    ud = uml.Data(um, x)
+    start = um.theta0.copy()
+    start[0] += 0.02
+    start[17] -= 0.02
+    say(f"case 4d newton fit precision={precision}")
+    r = uml.uml_fit(um, ud, start, edm_tol=1e-10 if precision == "fp64" else 1e-8,
+                    method=uml.UML_METHOD_NEWTON)
+    om = oracle.Model(desc)
+    ro = om.fit(x.astype(np.float64), start=start, edm_tol=1e-12, polish=1)
+    assert ro["status"] == 0
+    compare_fits(r, ro, om.free, 1e-5 if precision == "fp64" else 1e-3,
+                 1e-8 if precision == "fp64" else 1e-4, f"4d-newton-{precision}")
+    assert r["n_iter"] <= 6
+
+
+def test_newton_c1_mass_fit():
+    desc = W.mass1d()
+    x = rng_events(desc, 10_000, 2025, np.float64)
+    start = np.array(W.mass1d_start())
+    um = uml.Model(desc, "fp64")
+    ud = uml.Data(um, x)
+    say("case c1 newton")
+    r = uml.uml_fit(um, ud, start, edm_tol=1e-12, method=uml.UML_METHOD_NEWTON)
+    om = oracle.Model(desc)
+    ro = om.fit(x, start=start, edm_tol=1e-12, polish=1)
+    compare_fits(r, ro, om.free, 1e-6, 1e-8, "c1-newton")
+
+
 def test_gaussian_fit_reaches_closed_form_mle():
     rng = np.random.default_rng(4)
     x = rng.normal(5.28, 0.02, 20_000).reshape(1, -1)

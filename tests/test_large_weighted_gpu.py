@@ -1,0 +1,64 @@
+"""The 4-D model at 1e7 events with per-event weights w ~ U(0.5, 1.5):
+weighted fits in FP64 and in mixed precision, with the covariance from the
+Hessian pass, against the oracle.  The oracle's own minimum is reached from
+the FP64 fit's point by one Newton step with the oracle's gradient and
+Hessian there (exact to second order at that distance), and the oracle's
+uncertainties are sqrt(diag H^-1) at that point, or with the sandwich
+covariance H^-1 W2 H^-1 of weighted fits."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2505_12414_amd import datagen as G
+from paper_2505_12414_amd import uml
+from paper_2505_12414_amd import workloads as W
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(900)
+def test_weighted_1e7_fits_against_oracle():
+    n = 10_000_000
+    desc = W.angmass4d()
+    x = G.gen_angmass4d(n, 5150, dtype=np.float32)
+    w = G.uniform_weights(n, 5151)
+    fits = {}
+    for precision, edm in (("fp64", 1e-10), ("mixed", 1e-8)):
+        say(f"case weighted 1e7 fit precision={precision}")
+        um = uml.Model(desc, precision)
+        ud = uml.Data(um, x, weights=w)
+        r = uml.uml_fit(um, ud, um.theta0, edm_tol=edm)
+        say(f"  status {r['status_name']} n_iter {r['n_iter']} edm {r['edm']:.2e}")
+        assert r["status"] == 0
+        rs = uml.uml_fit(um, ud, um.theta0, edm_tol=edm, cov_kind=uml.UML_COV_SANDWICH)
+        assert np.array_equal(rs["theta"], r["theta"])
+        r["errors_sandwich"] = rs["errors"]
+        fits[precision] = r
+        del ud
+    om = oracle.Model(desc)
+    free = om.free
+    t64 = fits["fp64"]["theta"]
+    say("  oracle gradient and Hessian at the FP64 fit's point")
+    nll, g, h, bad = om.nll(x.astype(np.float64), t64, w=w.astype(np.float64), order=2)
+    assert bad == 0
+    H = h[np.ix_(free, free)]
+    C = np.linalg.inv(H)
+    t_or = t64.copy()
+    t_or[free] -= C @ g[free]
+    s_or = np.sqrt(np.diag(C))
+    w2, bad = om.w2(x.astype(np.float64), t64, w.astype(np.float64))
+    assert bad == 0
+    s_sw = np.sqrt(np.diag(C @ w2[np.ix_(free, free)] @ C))
+    for precision, r in fits.items():
+        dth = np.abs(r["theta"][free] - t_or[free]) / s_or
+        dsg = np.abs(r["errors"][free] - s_or) / s_or
+        dsw = np.abs(r["errors_sandwich"][free] - s_sw) / s_sw
+        say(f"  {precision}: |dtheta|/sigma max {dth.max():.2e} {np.round(dth, 8).tolist()}")
+        say(f"  {precision}: |dsigma|/sigma max {dsg.max():.2e} {np.round(dsg, 8).tolist()}")
+        say(f"  {precision}: sandwich |dsigma|/sigma max {dsw.max():.2e}")
+        lim = 1e-4 if precision == "fp64" else 1e-3
+        assert dth.max() <= lim
+        assert dsg.max() <= lim
+        assert dsw.max() <= lim
