@@ -69,6 +69,11 @@ def _load():
         lib.orc_nll.restype = C.c_long
         lib.orc_w2.argtypes = [C.POINTER(_Model), C.c_long, dp, dp, dp, dp]
         lib.orc_w2.restype = C.c_long
+        u64p = C.POINTER(C.c_uint64)
+        lib.orc_philox4x64.argtypes = [u64p, u64p, u64p]
+        lib.orc_philox4x64.restype = None
+        lib.orc_generate.argtypes = [C.POINTER(_Model), C.c_long, C.c_long, C.c_uint64, dp, dp]
+        lib.orc_generate.restype = C.c_long
         lib.orc_fit.argtypes = [C.POINTER(_Model), C.c_long, dp, dp, dp, ip,
                                 C.POINTER(_FitOpts), dp, C.POINTER(_FitInfo)]
         lib.orc_fit.restype = C.c_int
@@ -78,6 +83,16 @@ def _load():
 
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def philox4x64(ctr, key):
+    """One Philox4x64-10 block: four 64-bit words from a counter (4 words)
+    and a key (2 words)."""
+    c = (C.c_uint64 * 4)(*[int(v) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) for v in key])
+    o = (C.c_uint64 * 4)()
+    _load().orc_philox4x64(c, k, o)
+    return [int(v) for v in o]
 
 
 def _ncols(x, ndim):
@@ -163,6 +178,15 @@ class Model:
             wp = _dptr(w)
         out = np.zeros((self.npar, self.npar))
         bad = _load().orc_w2(C.byref(self._m), n, _dptr(x), wp, _dptr(th), _dptr(out))
+        return out, int(bad)
+
+    def generate(self, n, seed, theta=None, i0=0):
+        """Events i0 .. i0+n-1 of pseudo-experiment `seed` at theta: (ndim, n)
+        FP64 and the number of events that hit the attempt cap."""
+        th = np.ascontiguousarray(self.theta0 if theta is None else theta, dtype=np.float64)
+        out = np.zeros((self.ndim, n))
+        bad = _load().orc_generate(C.byref(self._m), int(i0), int(n), C.c_uint64(seed), _dptr(th),
+                                   _dptr(out))
         return out, int(bad)
 
     def fit(self, x, start=None, free=None, w=None, edm_tol=1e-6, max_iter=500, polish=0):

@@ -436,6 +436,178 @@ long orc_w2(const orc_model* m, long n, const double* x, const double* w,
 }
 
 /* ------------------------------------------------------------------ */
+/* pseudo-experiment generation                                        */
+/* ------------------------------------------------------------------ */
+
+/* Philox4x64 with 10 rounds (Salmon, Moraes, Dror and Shaw, "Parallel
+   random numbers: as easy as 1, 2, 3", SC11): a counter-based generator.
+   Each round multiplies words 0 and 2 by fixed odd constants, keeps the
+   128-bit products' halves and mixes them with words 1 and 3 and the key;
+   the key is advanced by two Weyl constants between rounds. */
+void orc_philox4x64(const unsigned long long ctr[4], const unsigned long long key[2],
+                    unsigned long long out[4]) {
+  const unsigned long long M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const unsigned long long W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  unsigned long long x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  unsigned long long k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    unsigned __int128 p0 = (unsigned __int128)M0 * x0;
+    unsigned __int128 p1 = (unsigned __int128)M1 * x2;
+    unsigned long long hi0 = (unsigned long long)(p0 >> 64), lo0 = (unsigned long long)p0;
+    unsigned long long hi1 = (unsigned long long)(p1 >> 64), lo1 = (unsigned long long)p1;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+/* The uniform stream of one event: blocks b = 0, 1, .. of Philox with
+   counter (b, event, 0, 0) and key (seed, 0), four 64-bit words each, each
+   word giving u = (top 53 bits + 1/2) / 2^53 in (0, 1). */
+typedef struct {
+  unsigned long long key[2], ctr[4], buf[4];
+  int pos;
+} ustream;
+
+static void us_init(ustream* s, unsigned long long seed, long event) {
+  s->key[0] = seed;
+  s->key[1] = 0;
+  s->ctr[0] = 0;
+  s->ctr[1] = (unsigned long long)event;
+  s->ctr[2] = s->ctr[3] = 0;
+  s->pos = 4;
+}
+
+static double us_next(ustream* s) {
+  if (s->pos == 4) {
+    orc_philox4x64(s->ctr, s->key, s->buf);
+    s->ctr[0] += 1;
+    s->pos = 0;
+  }
+  unsigned long long r = s->buf[s->pos++];
+  return ((double)(r >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+#define ORC_GEN_CAP 65536 /* accept-reject attempts per draw */
+
+/* Draws the dimensions of node id into xe; returns 0, or 1 if a draw hit
+   the attempt cap.  Sums pick a child with probability f / 1 - f; products
+   draw every child; leaves draw their dimensions: the Gaussian by the
+   Box-Muller transform with rejection outside the range, the exponential by
+   its inverse distribution function, the Chebyshev series and the P-wave
+   density by accept-reject under the sum of the absolute values of their
+   terms' coefficients times the terms' maxima. */
+static int gen_node(const orc_model* m, int id, const double* th, ustream* s, double* xe) {
+  const orc_node* nd = &m->node[id];
+  switch (nd->kind) {
+    case ORC_SUM: {
+      double f = th[nd->par[0]];
+      double u = us_next(s);
+      return gen_node(m, nd->child[u < f ? 0 : 1], th, s, xe);
+    }
+    case ORC_PROD: {
+      int bad = 0;
+      for (int c = 0; c < nd->nchild; ++c) bad |= gen_node(m, nd->child[c], th, s, xe);
+      return bad;
+    }
+    case ORC_GAUSS: {
+      int d = nd->dim[0];
+      double lo = m->lo[d], hi = m->hi[d], mu = th[nd->par[0]], sg = th[nd->par[1]];
+      for (int a = 0; a < ORC_GEN_CAP; ++a) {
+        double u1 = us_next(s), u2 = us_next(s);
+        double x = mu + sg * (sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2));
+        if (x >= lo && x <= hi) {
+          xe[d] = x;
+          return 0;
+        }
+      }
+      xe[d] = lo;
+      return 1;
+    }
+    case ORC_EXP: {
+      int d = nd->dim[0];
+      double lo = m->lo[d], hi = m->hi[d], lam = th[nd->par[0]], L = hi - lo;
+      double u = us_next(s);
+      double x = lam == 0.0 ? lo + u * L : lo + log1p(u * expm1(lam * L)) / lam;
+      xe[d] = x < lo ? lo : (x > hi ? hi : x);
+      return 0;
+    }
+    case ORC_CHEB: {
+      int d = nd->dim[0], k = nd->npar;
+      double lo = m->lo[d], hi = m->hi[d], L = hi - lo, env = 1.0;
+      for (int j = 0; j < k; ++j) env += fabs(th[nd->par[j]]);
+      for (int a = 0; a < ORC_GEN_CAP; ++a) {
+        double u1 = us_next(s), u2 = us_next(s);
+        double x = lo + u1 * L;
+        double t = (2.0 * x - lo - hi) / L, tm = 1.0, tj = t, v = 1.0;
+        for (int j = 1; j <= k; ++j) {
+          v += th[nd->par[j - 1]] * tj;
+          double tn = 2.0 * t * tj - tm;
+          tm = tj;
+          tj = tn;
+        }
+        if (u2 * env <= v) {
+          xe[d] = x;
+          return 0;
+        }
+      }
+      xe[d] = lo;
+      return 1;
+    }
+    case ORC_PWAVE: {
+      double FL = th[nd->par[0]];
+      double env = 0.75 * fabs(1.0 - FL) + fabs(FL) + 0.25 * fabs(1.0 - FL) + fabs(FL) +
+                   4.0 / 3.0 * fabs(th[nd->par[4]]);
+      for (int k = 1; k < 8; ++k)
+        if (k != 4) env += fabs(th[nd->par[k]]);
+      env *= 9.0 / (32.0 * M_PI); /* the value below carries the same factor */
+      val_t* o = (val_t*)malloc(sizeof(val_t));
+      int bad = 1;
+      for (int a = 0; a < ORC_GEN_CAP; ++a) {
+        double u1 = us_next(s), u2 = us_next(s), u3 = us_next(s), u4 = us_next(s);
+        xe[nd->dim[0]] = 2.0 * u1 - 1.0;
+        xe[nd->dim[1]] = 2.0 * u2 - 1.0;
+        xe[nd->dim[2]] = M_PI * (2.0 * u3 - 1.0);
+        leaf_pwave(m, nd, xe, th, 0, o);
+        if (u4 * env <= o->v) {
+          bad = 0;
+          break;
+        }
+      }
+      free(o);
+      if (bad) {
+        xe[nd->dim[0]] = m->lo[nd->dim[0]];
+        xe[nd->dim[1]] = m->lo[nd->dim[1]];
+        xe[nd->dim[2]] = m->lo[nd->dim[2]];
+      }
+      return bad;
+    }
+  }
+  return 1;
+}
+
+long orc_generate(const orc_model* m, long i0, long n, unsigned long long seed,
+                  const double* theta, double* x) {
+  long bad = 0;
+  double xe[ORC_MAXD];
+  for (long i = 0; i < n; ++i) {
+    ustream s;
+    us_init(&s, seed, i0 + i);
+    for (int d = 0; d < m->ndim; ++d) xe[d] = m->lo[d];
+    bad += gen_node(m, m->root, theta, &s, xe);
+    for (int d = 0; d < m->ndim; ++d) x[(long)d * n + i] = xe[d];
+  }
+  return bad;
+}
+
+/* ------------------------------------------------------------------ */
 /* BFGS fit                                                            */
 /* ------------------------------------------------------------------ */
 

@@ -4,8 +4,9 @@
  * A plain, slow, single-threaded FP64 CPU implementation of what the GPU
  * library computes: the normalised PDFs of the model catalogue, the unbinned
  * negative log-likelihood -sum_i w_i ln P(x_i | theta) (MoreFit paper, Eq. 1),
- * its analytic gradient and Hessian (Sec. 2.2), and a quasi-Newton (BFGS) fit
- * with a Hessian-based covariance (Sec. 2.1).
+ * its analytic gradient and Hessian (Sec. 2.2), a quasi-Newton (BFGS) fit
+ * with a Hessian-based covariance (Sec. 2.1), and the generation of
+ * pseudo-experiments from a model (Sec. 2.5).
  *
  * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
  * may load this.  It shares no code, header or constant with the GPU library.
@@ -74,6 +75,19 @@ long orc_nll(const orc_model* m, long n, const double* x, const double* w,
    (npar x npar, row-major); returns the count of events with P <= 0. */
 long orc_w2(const orc_model* m, long n, const double* x, const double* w,
             const double* theta, double* w2);
+
+/* Philox4x64-10 block of a counter and a key (the counter-based generator
+   of Salmon et al., SC11). */
+void orc_philox4x64(const unsigned long long ctr[4], const unsigned long long key[2],
+                    unsigned long long out[4]);
+
+/* Events i0 .. i0+n-1 of the pseudo-experiment `seed`, drawn from the model
+   at theta into x (SoA [ndim][n]).  Event i uses the uniform stream of
+   Philox counters (b, i, 0, 0), key (seed, 0), so any event can be drawn on
+   its own.  Returns the number of events whose sampling hit the attempt cap
+   (their values are the lower range edges). */
+long orc_generate(const orc_model* m, long i0, long n, unsigned long long seed,
+                  const double* theta, double* x);
 
 typedef struct {
   double edm_tol;  /* stop when 0.5 g^T V g < edm_tol                   */

@@ -465,3 +465,112 @@ def test_fraction_outside_unit_interval_is_outside_the_domain():
     for f in (0.0, 1.0):   # the closed ends are valid mixtures
         nll, _, _, bad = m.nll(x, np.array([5.28, 0.02, -1.5, f]))
         assert bad == 0 and math.isfinite(nll)
+
+
+# --------------------------------------------------------------------------
+# pseudo-experiment generation: the counter-based generator against NumPy's
+# Philox bit generator, samples against library distribution functions and
+# closed-form moments, fits to generated toys against their generating values
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ctr,key", [
+    ([0, 0, 0, 0], [0, 0]),
+    ([5, 0, 0, 0], [7, 9]),
+    ([2 ** 64 - 1, 3, 0, 0], [12345, 2 ** 63 + 11]),   # carry into the second word
+    ([17, 2 ** 40, 5, 1], [2 ** 64 - 1, 2 ** 64 - 1]),
+])
+def test_philox_matches_numpy_bit_generator(ctr, key):
+    """NumPy's Philox (4 x 64 bits, 10 rounds) advances its 256-bit counter
+    before each block: its first four words are the block of counter + 1."""
+    bg = np.random.Philox(counter=np.array(ctr, dtype=np.uint64), key=np.array(key, dtype=np.uint64))
+    ref = [int(v) for v in bg.random_raw(8)]
+    c = list(ctr)
+    for blk in range(2):
+        k = 0
+        while True:   # counter + 1 with carry
+            c[k] = (c[k] + 1) % 2 ** 64
+            if c[k] != 0:
+                break
+            k += 1
+        assert oracle.philox4x64(c, key) == ref[4 * blk:4 * blk + 4]
+
+
+def ks_pvalue(x, cdf):
+    return stats.kstest(x, cdf).pvalue
+
+
+def test_generated_gaussian_and_exponential_follow_their_distributions():
+    lo, hi = 5.0, 5.6
+    g = oracle.Model(gauss_model(lo, hi, 5.3, 0.1))       # both edges inside 3 sigma
+    x, bad = g.generate(100000, 11)
+    assert bad == 0 and x.min() >= lo and x.max() <= hi
+    tn = stats.truncnorm((lo - 5.3) / 0.1, (hi - 5.3) / 0.1, loc=5.3, scale=0.1)
+    assert ks_pvalue(x[0], tn.cdf) > 1e-3
+    e = oracle.Model(exp_model(lo, hi, -3.0))
+    x, bad = e.generate(100000, 12)
+    te = stats.truncexpon((hi - lo) * 3.0, loc=lo, scale=1 / 3.0)
+    assert bad == 0 and ks_pvalue(x[0], te.cdf) > 1e-3
+    e0 = oracle.Model(exp_model(lo, hi, 0.0))           # lambda = 0: uniform
+    x, _ = e0.generate(100000, 13)
+    assert ks_pvalue(x[0], stats.uniform(lo, hi - lo).cdf) > 1e-3
+
+
+@pytest.mark.parametrize("coeffs", [(0.3,), (0.1, 0.05), (0.1, -0.2, 0.05, 0.1)])
+def test_generated_chebyshev_follows_its_distribution(coeffs):
+    lo, hi = -1.0, 2.0
+    m = oracle.Model(cheb_model(lo, hi, coeffs))
+    x, bad = m.generate(100000, 21)
+    assert bad == 0
+    series = np.polynomial.chebyshev.Chebyshev([1.0, *coeffs], domain=[lo, hi])
+    prim = series.integ(lbnd=lo)
+    norm = prim(hi)
+    assert ks_pvalue(x[0], lambda v: prim(v) / norm) > 1e-3
+
+
+def test_generated_mass_mixture_follows_its_distribution():
+    lo, hi, mu, sg, lam, f = 5.0, 5.6, 5.28, 0.02, -1.5, 0.3
+    m = oracle.Model(W.mass1d())
+    x, bad = m.generate(200000, 31)
+    tn = stats.truncnorm((lo - mu) / sg, (hi - mu) / sg, loc=mu, scale=sg)
+    te = stats.truncexpon((hi - lo) * -lam, loc=lo, scale=1 / -lam)
+    # the exponential of the model rises or falls with lambda: e^{lam x} with
+    # lam < 0 falls, which is the truncated exponential of rate -lam
+    assert bad == 0 and ks_pvalue(x[0], lambda v: f * tn.cdf(v) + (1 - f) * te.cdf(v)) > 1e-3
+
+
+@pytest.mark.parametrize("ang", PWAVE_POINTS, ids=["fl-only", "workload", "all"])
+def test_generated_pwave_moments(ang):
+    """Sample moments of generated angles against the closed forms (within
+    five standard errors of the sample)."""
+    m = oracle.Model(W.pwave3d(ang))
+    x, bad = m.generate(400000, 41)
+    assert bad == 0
+    FL, S3, S4, S5, AFB, S7, S8, S9 = ang
+    cl, ck, ph = x
+    sl, sk = np.sqrt(1 - cl ** 2), np.sqrt(1 - ck ** 2)
+    for t, want in [(cl, 2.0 / 3.0 * AFB), (ck ** 2, (1 + 2 * FL) / 5.0),
+                    (sk ** 2 * sl ** 2 * np.cos(2 * ph), 0.32 * S3),
+                    (sk ** 2 * sl ** 2 * np.sin(2 * ph), 0.32 * S9),
+                    (4 * sk * ck * sl * cl * np.cos(ph), 0.32 * S4),
+                    (4 * sk * ck * sl * cl * np.sin(ph), 0.32 * S8),
+                    (2 * sk * ck * sl * np.cos(ph), 0.4 * S5),
+                    (2 * sk * ck * sl * np.sin(ph), 0.4 * S7)]:
+        se = t.std() / math.sqrt(t.size)
+        assert abs(t.mean() - want) < 5 * se, (t.mean(), want, se)
+
+
+def test_fits_to_generated_toys_are_unbiased():
+    """Oracle fits of 200 generated mass-model toys: pulls of mean ~0 and
+    width ~1 for every parameter."""
+    m = oracle.Model(W.mass1d())
+    truth = m.theta0.copy()
+    pulls = []
+    for k in range(200):
+        x, bad = m.generate(2000, 1000 + k)
+        assert bad == 0
+        r = m.fit(x, start=truth)
+        assert r["status"] == 0
+        pulls.append((r["theta"] - truth) / r["errors"])
+    p = np.array(pulls)
+    assert np.all(np.abs(p.mean(0)) < 0.3), p.mean(0)
+    assert np.all(np.abs(p.std(0) - 1.0) < 0.2), p.std(0)
