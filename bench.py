@@ -111,7 +111,7 @@ def headline(args, torch, uml, G, W):
         x = G.gen_mass1d(n, seed=SEED_DATA, dtype=dtype)
         truth = [5.28, 0.02, -1.5, 0.3]
     dev = torch.device("cuda:0")
-    model = uml.Model(desc, args.precision)
+    model = uml.Model(desc, args.precision, precompute=args.precompute)
     data = uml.Data(model, x)
     theta = torch.tensor(truth, dtype=torch.float64, device=dev)
     out = torch.empty(1 + model.n_free, dtype=torch.float64, device=dev)
@@ -137,8 +137,14 @@ def headline(args, torch, uml, G, W):
     value = n * args.steps / (gpu_ms * 1e-3)
 
     esize = 4 if args.precision == "mixed" else 8
-    kname = f"eval_kernel ({args.model}, {args.precision})"
-    if args.model == "angmass4d" and args.precision == "mixed":
+    kname = f"eval_kernel ({args.model}, {args.precision}{', precomputed terms' if args.precompute else ''})"
+    if args.precompute:   # 4 columns + 9 precomputed terms per event: a streaming kernel
+        nbytes = 13 * esize * n
+        achieved = nbytes / (ms_per_step * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                    "kernel": kname, "bytes_per_event": 13 * esize}
+    elif args.model == "angmass4d" and args.precision == "mixed":
         achieved = FLOP_PER_EVENT_4D * n / (ms_per_step * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
@@ -156,7 +162,7 @@ def headline(args, torch, uml, G, W):
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                     "kernel": kname, "bytes_per_event": esize}
-    if args.model == "angmass4d" and args.marginal_events > n:
+    if args.model == "angmass4d" and args.marginal_events > n and not args.precompute:
         # the per-event cost alone: a second, larger dataset timed the same
         # way; the difference removes the fixed cost of a launch (dispatch,
         # constant check, reduction chain), which dominates at 1e6 events
@@ -182,7 +188,7 @@ def headline(args, torch, uml, G, W):
                                 "fixed_us": round(us1 - n * per_event_s * 1e6, 3),
                                 "achieved": round(tf, 3), "frac": round(tf / peak, 4)}
         del data2, x2
-    wl_key = f"{args.model}-{n}-{args.precision}"
+    wl_key = f"{args.model}-{n}-{args.precision}" + ("-precomputed" if args.precompute else "")
     traffic = counted_traffic(wl_key)
     roofline["traffic"] = traffic
     roofline["traffic_key"] = wl_key
@@ -197,29 +203,48 @@ def headline(args, torch, uml, G, W):
 
 
 class Stream:
-    """The request stream: sizes, arrival times and events.  The first
-    n_indep requests carry independently generated events (seed SEED_TOY0+i)
-    and are the ones pulls are computed from; the others are seeded windows of
-    one large pool drawn from the same model."""
+    """The request stream: sizes, arrival times and events.  Toy i is the
+    pseudo-experiment with seed SEED_TOY0 + i.  With device generation (the
+    default) each request is drawn on the GPU from its seed.  With host
+    events, the first n_indep requests carry independently generated events
+    and the others are seeded windows of one large pool from the same model;
+    pulls then come from the first n_indep toys only."""
 
     def __init__(self, args, G):
         rng = np.random.default_rng(SEED_STREAM)
         k = args.serving_fits
+        self.device = args.serving_source == "device"
         self.sizes = np.floor(np.exp(rng.uniform(np.log(500), np.log(50000), k))).astype(np.int64)
         gaps = rng.exponential(1.0 / args.rate, k)
         self.arrivals = np.cumsum(gaps) - gaps[0]
+        self.offsets = rng.integers(0, max(args.pool_events, 60000) - 50000, k)
+        if self.device:
+            self.n_indep = k
+            return
         self.n_indep = min(args.pull_fits, k)
         pool_n = max(args.pool_events, 60000)
         self.pool = G.gen_angmass4d(pool_n, SEED_POOL, dtype=np.float32)
-        self.offsets = rng.integers(0, pool_n - 50000, k)
         self.indep = [G.gen_angmass4d(int(self.sizes[i]), SEED_TOY0 + i, dtype=np.float32)
                       for i in range(self.n_indep)]
+
+    def seed(self, i):
+        return SEED_TOY0 + i
 
     def events(self, i):
         if i < self.n_indep:
             return self.indep[i]
         o = int(self.offsets[i])
         return self.pool[:, o:o + int(self.sizes[i])]
+
+    def submit(self, srv, i):
+        if self.device:
+            return srv.submit_generated(int(self.sizes[i]), self.seed(i))
+        return srv.submit(self.events(i))
+
+    def data(self, uml, um, i):
+        if self.device:
+            return uml.Data.generate(um, int(self.sizes[i]), self.seed(i))
+        return uml.Data(um, self.events(i))
 
 
 def _pct(a, q):
@@ -251,7 +276,7 @@ def run_server(uml, um, st, k, open_loop, slots, budget):
             d = t0 + st.arrivals[i] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-        idx[srv.submit(st.events(i))] = i
+        idx[st.submit(srv, i)] = i
     th.join()
     t_end = max(t_recv.values())
     stats = srv.stats()
@@ -275,7 +300,7 @@ def run_loop(uml, um, st, k, open_loop):
             d = t0 + st.arrivals[i] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-        data = uml.Data(um, st.events(i))
+        data = st.data(uml, um, i)
         r = uml.uml_fit(um, data)
         data.close()
         t = time.perf_counter()
@@ -306,8 +331,9 @@ def serving(args, uml, G, W):
     budget = args.budget_mb << 20
     s_open = run_server(uml, um, st, k, True, args.slots, budget)
     s_sat = run_server(uml, um, st, k, False, args.slots, budget)
-    l_sat = run_loop(uml, um, st, kl, False)
-    l_open = run_loop(uml, um, st, kl, True)
+    empty = {"fits_per_s": 0.0, "p50_ms": 0.0, "p99_ms": 0.0, "elapsed_s": 0.0, "results": []}
+    l_sat = run_loop(uml, um, st, kl, False) if kl else empty
+    l_open = run_loop(uml, um, st, kl, True) if kl else empty
     # equal accuracy: the fits of both paths on the requests both ran
     dev = 0.0
     for a, b in zip(s_sat["results"][:kl], l_sat["results"]):
@@ -325,6 +351,8 @@ def serving(args, uml, G, W):
             o["peak_resident_mb"] = round(s["peak_resident_bytes"] / 2**20, 1)
             o["budget_waits"] = s["budget_waits"]
             o["iterations"] = s["iterations"]
+            o["worker_s"] = {"admit": round(s["t_admit_s"], 3), "iterate": round(s["t_iterate_s"], 3),
+                             "retire": round(s["t_retire_s"], 3)}
         return o
 
     return {"desc": desc, "stream": st, "truth": truth, "free": free,
@@ -336,17 +364,33 @@ def serving(args, uml, G, W):
                 "fits": k, "loop_fits": kl, "slots": args.slots, "hbm_budget_mb": args.budget_mb,
                 "server_open_loop": summary(s_open), "server_saturated": summary(s_sat),
                 "loop_open_loop": summary(l_open), "loop_saturated": summary(l_sat),
-                "capacity_ratio": round(s_sat["fits_per_s"] / l_sat["fits_per_s"], 2),
+                "capacity_ratio": (round(s_sat["fits_per_s"] / l_sat["fits_per_s"], 2)
+                                   if l_sat["fits_per_s"] else None),
                 "max_dtheta_over_sigma_server_vs_loop": dev,
                 "statuses": statuses,
                 "pulls": pulls(s_open["results"][:st.n_indep], truth, free),
-                "events": ("first %d requests independently generated (seed %d+i); the rest are "
+                "events": ("every request drawn on the GPU from its own seed %d+i" % SEED_TOY0
+                           if st.device else
+                           "first %d requests independently generated (seed %d+i); the rest are "
                            "seeded windows of a %d-event pool from the same model"
                            % (st.n_indep, SEED_TOY0, st.pool.shape[1]))}}
 
 
 # ---------------------------------------------------------------------------
 # CPU baseline: the oracle on a bounded sample of the same work
+
+
+def fp32_storage(x64, desc):
+    """FP32 storage of FP64 event values: the nearest value, moved one step
+    inwards where rounding left the dimension's range."""
+    out = x64.astype(np.float32)
+    for d, dim in enumerate(desc["dims"]):
+        f = out[d]
+        up = f.astype(np.float64) > dim["hi"]
+        f[up] = np.nextafter(f[up], np.float32(-np.inf))
+        dn = f.astype(np.float64) < dim["lo"]
+        f[dn] = np.nextafter(f[dn], np.float32(np.inf))
+    return out
 
 
 def cpu_baseline(args, H, S):
@@ -373,7 +417,11 @@ def cpu_baseline(args, H, S):
     n_fit, t, dmax, emax, nev = 0, 0.0, 0.0, 0.0, 0
     t0 = time.perf_counter()
     while n_fit < st.n_indep and t < args.cpu_seconds:
-        x = st.indep[n_fit].astype(np.float64)
+        if st.device:   # the oracle draws the same toy; stored in FP32 as the GPU stores it
+            xg, _ = om4.generate(int(st.sizes[n_fit]), st.seed(n_fit))
+            x = fp32_storage(xg, S["desc"]).astype(np.float64)
+        else:
+            x = st.indep[n_fit].astype(np.float64)
         r = om4.fit(x, S["truth"])
         g = S["server_results"][n_fit]
         if r["status"] == 0 and g["status"] == 0:
@@ -384,7 +432,7 @@ def cpu_baseline(args, H, S):
         n_fit += 1
         t = time.perf_counter() - t0
     fits = {"value": round(n_fit / t, 2), "unit": "fits/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_fit} independently generated toys ({nev} events), FP64 BFGS "
+            "sample": f"first {n_fit} toys of the stream ({nev} events), FP64 BFGS "
                       f"to EDM < 1e-6 and Hessian, {t:.1f} s, one thread",
             "max_dtheta_over_sigma_vs_server": dmax,
             "max_rel_error_of_sigma_vs_server": emax}
@@ -406,10 +454,15 @@ def main():
     ap.add_argument("--rate", type=float, default=500.0, help="open-loop arrival rate, fits/s")
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--budget-mb", type=int, default=256, help="server device-memory budget")
-    ap.add_argument("--pull-fits", type=int, default=200)
+    ap.add_argument("--pull-fits", type=int, default=200,
+                    help="host events only: independently generated toys for the pulls")
+    ap.add_argument("--serving-source", default="device", choices=["device", "host"],
+                    help="toy events drawn on the GPU from each request's seed, or uploaded")
     ap.add_argument("--pool-events", type=int, default=1 << 22)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precompute", action="store_true",
+                    help="4-D model with the P-wave's event-only terms stored per event")
     ap.add_argument("--marginal-events", type=int, default=4_000_000,
                     help="second dataset size for the per-event (marginal) rate; 0: skip")
     args = ap.parse_args()

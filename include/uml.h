@@ -51,6 +51,7 @@ extern "C" {
 #define UML_E_BUDGET -8          /* server: request exceeds the memory budget */
 #define UML_E_QUEUE_FULL -9      /* server: too many pending requests         */
 #define UML_E_TIMEOUT -10        /* server: nothing finished within timeout   */
+#define UML_E_GENERATION -11     /* generation: an accept-reject draw hit its cap */
 
 /* ---- limits ------------------------------------------------------------ */
 #define UML_MAX_DIMS 8
@@ -112,7 +113,15 @@ typedef struct {
   const uml_node* nodes;
   int32_t root;
   int32_t precision; /* UML_FP64 or UML_MIXED */
+  int32_t flags;     /* UML_MODEL_PRECOMPUTE_ANGULAR or 0 */
 } uml_model_desc;
+
+/* The event-only terms of the P-wave density (the eight angular functions of
+ * Eq. 4 and the F_L-free term) are computed once per dataset and stored as
+ * nine extra columns, which the event kernel reads instead of recomputing
+ * them (the paper's optimisation of event-dependent terms, Sec. 2.4.2).  For
+ * models with one P-wave factor. */
+#define UML_MODEL_PRECOMPUTE_ANGULAR 1
 
 typedef struct uml_model uml_model;
 typedef struct uml_data uml_data;
@@ -141,6 +150,24 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
                     const void* w, int32_t flags, void* stream, uml_data** out);
 void uml_data_destroy(uml_data* d);
 int64_t uml_data_n_events(const uml_data* d);
+
+/* A pseudo-experiment drawn on the device (the toy studies of Sec. 2.5): n
+ * events of the model at theta_all (NULL: the description's values), event i
+ * drawn from its own counter-based stream (Philox4x64-10 at counters
+ * (b, i, 0, 0), key (seed, 0)), so the events depend only on (seed, i).  Sums
+ * pick a child by their fraction, products draw every child, Gaussians by
+ * Box-Muller with rejection outside the range, exponentials by their inverse
+ * distribution function, Chebyshev series and the P-wave density by
+ * accept-reject.  Values are stored in the model's arithmetic (FP32 for
+ * UML_MIXED: the nearest FP32 value inside the range).  Returns
+ * UML_E_INVALID for a fraction outside [0, 1] or a width <= 0, and
+ * UML_E_GENERATION if an accept-reject draw needed more than 65536 attempts.
+ * Complete when the call returns. */
+int uml_data_generate(const uml_model* m, int64_t n, uint64_t seed, const double* theta_all,
+                      void* stream, uml_data** out);
+/* Copies the stored event columns to host columns cols[d] (model order) of
+ * the storage type (FP32 for UML_MIXED models, FP64 otherwise). */
+int uml_data_download(const uml_data* d, void* const* cols, void* stream);
 
 /* ---- evaluation (Eq. 1 and its derivatives) -----------------------------
  * Synchronous: return when the results are in the host buffers. */
@@ -190,7 +217,8 @@ enum {
   UML_FIT_LINESEARCH_FAIL = 2,
   UML_FIT_HESSIAN_NOT_PD = 3,
   UML_FIT_PDF_NONPOSITIVE = 4,
-  UML_FIT_CANCELLED = 5
+  UML_FIT_CANCELLED = 5,
+  UML_FIT_GENERATION_FAILED = 6 /* server: the request's events could not be drawn */
 };
 
 typedef struct {
@@ -236,6 +264,11 @@ typedef struct {
   int32_t dtype;           /* UML_F32 or UML_F64                             */
   const void* w;           /* host weights or NULL                           */
   const double* start;     /* n_params start values, or NULL for the model's */
+  int32_t generate;        /* non-zero: ignore cols/dtype/w and draw the
+                              n_events events on the device, as
+                              uml_data_generate does with this seed           */
+  uint64_t seed;
+  const double* gen_theta; /* parameters to draw at (NULL: the model's)      */
 } uml_request;
 
 typedef struct {
@@ -244,6 +277,9 @@ typedef struct {
   int64_t resident_bytes;  /* device bytes held by admitted requests          */
   int64_t peak_resident_bytes;
   int64_t budget_waits;    /* admission passes that stopped for lack of memory */
+  double t_admit_s;        /* worker time admitting requests (upload, start metric) */
+  double t_iterate_s;      /* worker time in batched iterations (graph replays)   */
+  double t_retire_s;       /* worker time retiring fits (final Hessian, results)  */
 } uml_server_stats;
 
 void uml_server_options_default(uml_server_options* o);

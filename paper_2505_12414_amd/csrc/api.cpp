@@ -100,7 +100,9 @@ DataLayout data_layout(const Plan& P, int64_t n, bool weighted) {
   DataLayout L{};
   const size_t esz = P.precision == UML_MIXED ? 4 : 8;
   L.stride = align_up(std::max<int64_t>(n, 1), 64);
-  L.bytes_events = size_t(L.stride) * esz * (P.ndim + (weighted ? 1 : 0));
+  // columns: the dimensions, the weights, then any precomputed terms (the
+  // host buffer of an upload fills the first part)
+  L.bytes_events = size_t(L.stride) * esz * (P.ncol + (weighted ? 1 : 0));
   L.E = events_per_thread(n, P.precision);
   const int64_t tsize = int64_t(L.E) * kBlock;
   L.n_tiles = int(std::max<int64_t>(1, (n + tsize - 1) / tsize));
@@ -137,6 +139,8 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
   for (int kd = 0; kd < P.ndim; ++kd)
     J.col[kd] = static_cast<char*>(d_events) + size_t(kd) * L.stride * esz;
   J.w = weighted ? static_cast<char*>(d_events) + size_t(P.ndim) * L.stride * esz : nullptr;
+  for (int kc = P.ndim; kc < P.ncol; ++kc)
+    J.col[kc] = static_cast<char*>(d_events) + size_t(kc + (weighted ? 1 : 0)) * L.stride * esz;
   J.n = n;
   J.n_tiles = L.n_tiles;
   J.events_per_thread = L.E;
@@ -150,11 +154,86 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
   J.npar = P.npar;
 }
 
-hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s) {
-  hipError_t e = hipMemcpyAsync(d->d_events, host.data(), host.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemsetAsync(d->d_work, 0, L.o_part, s);
+// The work area of a freshly placed dataset: counters and caches cleared,
+// the job descriptor copied.
+hipError_t data_init_work(uml_data* d, const DataLayout& L, hipStream_t s) {
+  const Plan& P = d->model->plan;
+  if (P.pre_fac >= 0 && d->n > 0) {  // the precomputed event-only terms
+    const FactorPlan& F = P.fac[P.pre_fac];
+    PrecomputeArgs a{};
+    for (int k = 0; k < 3; ++k) a.in[k] = d->job.col[F.dim[k]];
+    for (int k = 0; k < kPWaveTerms; ++k) a.out[k] = const_cast<void*>(d->job.col[F.pre + k]);
+    a.n = d->n;
+    launch_pwave_terms(a, P.precision, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipMemsetAsync(d->d_work, 0, L.o_part, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &d->job, sizeof(Job), hipMemcpyHostToDevice, s);
   return e;
+}
+
+hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s) {
+  hipError_t e = hipMemcpyAsync(d->d_events, host.data(), host.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = data_init_work(d, L, s);
+  return e;
+}
+
+// Parameters a model can be sampled at: fractions in [0, 1], Gaussian
+// widths > 0, everything finite.
+int check_generation_theta(const uml_model* m, const double* th, const char* fn) {
+  const GenPlan& G = m->gplan;
+  for (int k = 0; k < G.npar; ++k)
+    if (!std::isfinite(th[k]))
+      return set_error(UML_E_INVALID, std::string(fn) + ": parameter " + std::to_string(k) + " is not finite");
+  for (int i = 0; i < G.nnode; ++i) {
+    const GenNode& nd = G.node[i];
+    if (nd.kind == UML_SUM && !(th[nd.par[0]] >= 0.0 && th[nd.par[0]] <= 1.0))
+      return set_error(UML_E_INVALID, std::string(fn) + ": a fraction is outside [0, 1]");
+    if (nd.kind == UML_GAUSS && !(th[nd.par[1]] > 0.0))
+      return set_error(UML_E_INVALID, std::string(fn) + ": a Gaussian width is not positive");
+  }
+  return UML_OK;
+}
+
+GenOut gen_out(const uml_data* d, unsigned int* d_bad) {
+  GenOut o{};
+  for (int kd = 0; kd < d->model->plan.ndim; ++kd) o.col[kd] = const_cast<void*>(d->job.col[kd]);
+  o.n = d->n;
+  o.bad = d_bad;
+  return o;
+}
+
+// A dataset's device memory (events | work area | Hessian workspace, one
+// allocation) and pinned staging block; the caller fills the events.
+static int data_alloc(const uml_model* m, int64_t n, bool weighted, const DataLayout& L, uml_data** out,
+                      const char* fn) {
+  uml_data* d = new (std::nothrow) uml_data();
+  if (!d) return set_error(UML_E_NOMEM, std::string(fn) + ": out of host memory");
+  int hess_tiles = 0;
+  const size_t o_work = align_up(L.bytes_events, 256), o_hess = o_work + align_up(L.bytes_work, 256);
+  const size_t hbytes = m->d_hplan ? hess_work_bytes(m, n, &hess_tiles) : 0;
+  hipError_t e = hipMalloc(&d->d_alloc, o_hess + hbytes);
+  if (e != hipSuccess) {
+    delete d;
+    return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
+                     std::string(fn) + ": device buffer: " + hipGetErrorString(e));
+  }
+  d->h_stage = pinned_stage_get();
+  if (!d->h_stage) {
+    (void)hipFree(d->d_alloc);
+    delete d;
+    return set_error(UML_E_NOMEM, std::string(fn) + ": pinned staging");
+  }
+  char* base = static_cast<char*>(d->d_alloc);
+  data_bind(d, m, n, weighted, L, base, base + o_work);
+  if (hbytes) {
+    d->d_hwork = base + o_hess;
+    d->hess_tiles = hess_tiles;
+  }
+  d->owns_memory = 1;
+  *out = d;
+  return UML_OK;
 }
 
 }  // namespace uml
@@ -191,15 +270,39 @@ int uml_model_create(const uml_model_desc* desc, uml_model** out) {
   m->theta0.resize(desc->n_params);
   for (int k = 0; k < desc->n_params; ++k) m->theta0[k] = desc->params[k].value;
   const bool have_hess = build_hess_plan(m->plan, m->hplan, m->hess_err);
+  GenPlan& G = m->gplan;
+  G = GenPlan{};
+  G.nnode = desc->n_nodes;
+  G.root = desc->root;
+  G.ndim = desc->n_dims;
+  G.npar = desc->n_params;
+  for (int i = 0; i < desc->n_nodes; ++i) {
+    const uml_node& s = desc->nodes[i];
+    GenNode& g = G.node[i];
+    g.kind = s.kind;
+    for (int k = 0; k < 3; ++k) g.dim[k] = s.dims[k];
+    g.npar = s.n_params;
+    for (int k = 0; k < 8; ++k) g.par[k] = s.params[k];
+    g.nchild = s.n_children;
+    for (int k = 0; k < 4; ++k) g.child[k] = s.children[k];
+  }
+  for (int ud = 0; ud < desc->n_dims; ++ud) {
+    G.lo[ud] = desc->dims[ud].lo;
+    G.hi[ud] = desc->dims[ud].hi;
+    G.col_of_user[ud] = m->plan.dim_of_user[ud];
+  }
   hipError_t e = hipGetDevice(&m->device);
   if (e == hipSuccess) e = hipMalloc(&m->d_plan, sizeof(Plan));
   if (e == hipSuccess) e = hipMemcpy(m->d_plan, &m->plan, sizeof(Plan), hipMemcpyHostToDevice);
   if (e == hipSuccess && have_hess) e = hipMalloc(&m->d_hplan, sizeof(HessPlan));
   if (e == hipSuccess && have_hess)
     e = hipMemcpy(m->d_hplan, &m->hplan, sizeof(HessPlan), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&m->d_gplan, sizeof(GenPlan));
+  if (e == hipSuccess) e = hipMemcpy(m->d_gplan, &m->gplan, sizeof(GenPlan), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (m->d_plan) (void)hipFree(m->d_plan);
     if (m->d_hplan) (void)hipFree(m->d_hplan);
+    if (m->d_gplan) (void)hipFree(m->d_gplan);
     delete m;
     return set_error(UML_E_HIP, std::string("uml_model_create: ") + hipGetErrorString(e));
   }
@@ -212,6 +315,7 @@ void uml_model_destroy(uml_model* m) {
   if (m->d_plan) (void)hipFree(m->d_plan);
   if (m->d_hplan) (void)hipFree(m->d_hplan);
   if (m->d_fitws) (void)hipFree(m->d_fitws);
+  if (m->d_gplan) (void)hipFree(m->d_gplan);
   delete m;
 }
 
@@ -259,34 +363,73 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
   int rc = convert_events(P, n, n > 0 ? src.data() : nullptr, dtype, wsrc, host, "uml_data_create");
   if (rc != UML_OK) return rc;
   const DataLayout L = data_layout(P, n, w != nullptr);
-  uml_data* d = new (std::nothrow) uml_data();
-  if (!d) return set_error(UML_E_NOMEM, "uml_data_create: out of host memory");
-  auto fail = [&](hipError_t e, const char* what) {
-    if (d->d_alloc) (void)hipFree(d->d_alloc);
-    if (d->h_stage) pinned_stage_put(d->h_stage);
-    delete d;
-    return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
-                     std::string("uml_data_create: ") + what + ": " + hipGetErrorString(e));
-  };
-  // one device allocation: events | work area | Hessian workspace
-  int hess_tiles = 0;
-  const size_t o_work = align_up(L.bytes_events, 256), o_hess = o_work + align_up(L.bytes_work, 256);
-  const size_t hbytes = m->d_hplan ? hess_work_bytes(m, n, &hess_tiles) : 0;
-  hipError_t e = hipMalloc(&d->d_alloc, o_hess + hbytes);
-  if (e != hipSuccess) return fail(e, "device buffer");
-  char* base = static_cast<char*>(d->d_alloc);
-  d->h_stage = pinned_stage_get();
-  if (!d->h_stage) return fail(hipErrorOutOfMemory, "pinned staging");
-  data_bind(d, m, n, w != nullptr, L, base, base + o_work);
-  if (hbytes) {
-    d->d_hwork = base + o_hess;
-    d->hess_tiles = hess_tiles;
-  }
-  e = data_upload(d, L, host, s);
+  uml_data* d = nullptr;
+  rc = data_alloc(m, n, w != nullptr, L, &d, "uml_data_create");
+  if (rc != UML_OK) return rc;
+  hipError_t e = data_upload(d, L, host, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return fail(e, "upload");
-  d->owns_memory = 1;
+  if (e != hipSuccess) {
+    uml_data_destroy(d);
+    return set_error(UML_E_HIP, std::string("uml_data_create: upload: ") + hipGetErrorString(e));
+  }
   *out = d;
+  return UML_OK;
+}
+
+int uml_data_generate(const uml_model* m, int64_t n, uint64_t seed, const double* theta_all,
+                      void* stream, uml_data** out) {
+  if (!out) return set_error(UML_E_INVALID, "uml_data_generate: out is NULL");
+  *out = nullptr;
+  if (!m) return set_error(UML_E_INVALID, "uml_data_generate: model is NULL");
+  if (n < 0) return set_error(UML_E_INVALID, "uml_data_generate: negative event count");
+  const Plan& P = m->plan;
+  const double* th = theta_all ? theta_all : m->theta0.data();
+  int rc = check_generation_theta(m, th, "uml_data_generate");
+  if (rc != UML_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DataLayout L = data_layout(P, n, false);
+  uml_data* d = nullptr;
+  rc = data_alloc(m, n, false, L, &d, "uml_data_generate");
+  if (rc != UML_OK) return rc;
+  // the output slot doubles as the failure counter until the work area is
+  // initialised
+  unsigned int* d_bad = reinterpret_cast<unsigned int*>(d->d_out);
+  unsigned int* h_bad = reinterpret_cast<unsigned int*>(d->h_stage + UML_MAX_PARAMS);
+  std::memcpy(d->h_stage, th, sizeof(double) * P.npar);
+  hipError_t e = hipMemcpyAsync(d->d_theta, d->h_stage, sizeof(double) * P.npar, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(d_bad, 0, sizeof(unsigned int), s);
+  if (e == hipSuccess) {
+    launch_generate(m->d_gplan, d->d_theta, seed, gen_out(d, d_bad), P.precision, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h_bad, d_bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = data_init_work(d, L, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    uml_data_destroy(d);
+    return set_error(UML_E_HIP, std::string("uml_data_generate: ") + hipGetErrorString(e));
+  }
+  if (*h_bad) {
+    const unsigned bad = *h_bad;
+    uml_data_destroy(d);
+    return set_error(UML_E_GENERATION, "uml_data_generate: " + std::to_string(bad) +
+                                           " events needed more accept-reject attempts than the cap");
+  }
+  *out = d;
+  return UML_OK;
+}
+
+int uml_data_download(const uml_data* d, void* const* cols, void* stream) {
+  if (!d || (d->n > 0 && !cols)) return set_error(UML_E_INVALID, "uml_data_download: null argument");
+  const Plan& P = d->model->plan;
+  const size_t esz = P.precision == UML_MIXED ? 4 : 8;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int ud = 0; ud < P.ndim && d->n > 0; ++ud) {
+    if (!cols[ud]) return set_error(UML_E_INVALID, "uml_data_download: column pointer is NULL");
+    UML_HIP_CHECK(hipMemcpyAsync(cols[ud], d->job.col[P.dim_of_user[ud]], size_t(d->n) * esz,
+                                 hipMemcpyDeviceToHost, s));
+  }
+  UML_HIP_CHECK(hipStreamSynchronize(s));
   return UML_OK;
 }
 

@@ -150,6 +150,31 @@ struct Cheb {
   }
 };
 
+// The event-only terms of the P-wave density of one event (see PWave):
+// u0 and the eight angular terms m.  One function for the kernel that
+// recomputes them and for the kernel that stores them, so both give the same
+// values.
+template <class T>
+__device__ __forceinline__ void pwave_terms(T cl, T ck, T ph, T& u0, T (&m)[8]) {
+  const T sl2 = fma(-cl, cl, T(1));  // sin^2 theta_l
+  const T sk2 = fma(-ck, ck, T(1));  // sin^2 theta_K
+  const T skl2 = sk2 * sl2;
+  const T skl = k_sqrt(skl2);        // sin theta_K sin theta_l
+  T sp, cp;
+  k_sincos(ph, sp, cp);
+  const T w = ck * skl;              // sin 2K sin l / 2
+  const T wc = w * cl;               // sin 2K sin 2l / 4
+  u0 = fma(T(-0.5), skl2, sk2);
+  m[0] = fma((ck + ck) * ck, sl2, -u0);  // u1 - u0
+  m[1] = skl2 * fma(cp + cp, cp, T(-1)); // S3: sin^2K sin^2l cos 2phi
+  m[2] = wc * cp;                        // S4 / 4
+  m[3] = w * cp;                         // S5 / 2
+  m[4] = sk2 * cl;                       // AFB / (4/3)
+  m[5] = w * sp;                         // S7 / 2
+  m[6] = wc * sp;                        // S8 / 4
+  m[7] = skl2 * (sp * cp);               // S9 / 2
+}
+
 // P-wave angular density (Eq. 4) in dimensions (cos theta_l, cos theta_K, phi).
 // Written as  v = c0 u0 + c1 (u1 - u0) + sum_k c_{k+1} b_k  with
 //   u0 = sin^2 K (3/4 + cos 2l / 4) = sin^2 K (1 - sin^2 l / 2),
@@ -171,27 +196,38 @@ struct PWave {
   }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
-    const T cl = xs[D0], ck = xs[D1], ph = xs[D2];
-    const T sl2 = fma(-cl, cl, T(1));  // sin^2 theta_l
-    const T sk2 = fma(-ck, ck, T(1));  // sin^2 theta_K
-    const T skl2 = sk2 * sl2;
-    const T skl = k_sqrt(skl2);        // sin theta_K sin theta_l
-    T sp, cp;
-    k_sincos(ph, sp, cp);
-    const T w = ck * skl;              // sin 2K sin l / 2
-    const T wc = w * cl;               // sin 2K sin 2l / 4
-    const T u0 = fma(T(-0.5), skl2, sk2);
-    m[0] = fma((ck + ck) * ck, sl2, -u0);  // u1 - u0
-    m[1] = skl2 * fma(cp + cp, cp, T(-1)); // S3: sin^2K sin^2l cos 2phi
-    m[2] = wc * cp;                        // S4 / 4
-    m[3] = w * cp;                         // S5 / 2
-    m[4] = sk2 * cl;                       // AFB / (4/3)
-    m[5] = w * sp;                         // S7 / 2
-    m[6] = wc * sp;                        // S8 / 4
-    m[7] = skl2 * (sp * cp);               // S9 / 2
+    T u0, mm[8];
+    pwave_terms(xs[D0], xs[D1], xs[D2], u0, mm);
     T val = c[0] * u0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) val = fma(c[1 + k], m[k], val);
+    for (int k = 0; k < 8; ++k) {
+      m[k] = mm[k];
+      val = fma(c[1 + k], mm[k], val);
+    }
+    v = val;
+    (void)e;
+  }
+};
+
+// The P-wave density with its event-only terms read from the nine stored
+// columns B .. B+8 (u0, then the eight angular terms), computed once per
+// dataset (the optimisation of event-dependent terms, Sec. 2.4.2).
+template <int B>
+struct PWavePre {
+  static constexpr int kind = FK_PWAVE, order = 0;
+  static constexpr int ncst = fk_ncst(FK_PWAVE, 0), nmom = fk_nmom(FK_PWAVE, 0);
+  static constexpr bool expo = false;
+  static constexpr int maxdim = B + kPWaveTerms - 1;
+  static constexpr unsigned shift_mask = 0;
+  static std::string sig() { return "Q" + std::to_string(B); }
+  template <class T>
+  __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
+    T val = c[0] * xs[B];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      m[k] = xs[B + 1 + k];
+      val = fma(c[1 + k], m[k], val);
+    }
     v = val;
     (void)e;
   }
@@ -753,9 +789,9 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   T c[S::ncst];
 #pragma unroll
   for (int i = 0; i < S::ncst; ++i) c[i] = P::consts(gc)[i];
-  T xref[S::ndim];
+  T xref[S::ndim];  // only shifted dimensions (all below UML_MAX_DIMS) have one
 #pragma unroll
-  for (int d = 0; d < S::ndim; ++d) xref[d] = P::xrefs(gc)[d];
+  for (int d = 0; d < S::ndim; ++d) xref[d] = ((S::shift_mask >> d) & 1u) ? P::xrefs(gc)[d] : T(0);
   bool eq = true;
   if (lane < J.npar)
     eq = __double_as_longlong(th[lane]) == __double_as_longlong(gc->theta[lane]);
@@ -766,7 +802,8 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
 #pragma unroll
     for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
 #pragma unroll
-    for (int d = 0; d < S::ndim; ++d) xref[d] = to_sgpr(P::xrefs(&s_cb)[d]);
+    for (int d = 0; d < S::ndim; ++d)
+      xref[d] = ((S::shift_mask >> d) & 1u) ? to_sgpr(P::xrefs(&s_cb)[d]) : T(0);
   }
 
   T acc[K];
@@ -909,9 +946,36 @@ static const Family* families() {
       make_family<Shape<Comp<Gauss<0>, PWave<1, 2, 3>>>>(),                  // 4-D signal
       make_family<Shape<Comp<Exp<0>, Cheb<1, 2>, Cheb<2, 2>, Cheb<3, 2>>,  // 4-D model
                         Comp<Gauss<0>, PWave<1, 2, 3>>>>(),
+      // the same with the P-wave's event-only terms precomputed
+      make_family<Shape<Comp<PWavePre<3>>>>(),
+      make_family<Shape<Comp<Gauss<0>, PWavePre<4>>>>(),
+      make_family<Shape<Comp<Exp<0>, Cheb<1, 2>, Cheb<2, 2>, Cheb<3, 2>>, Comp<Gauss<0>, PWavePre<4>>>>(),
       Family{"", 0, 0, nullptr, nullptr},
   };
   return table;
+}
+
+// The stored P-wave terms of a dataset, one event per thread.
+template <class T>
+__global__ __launch_bounds__(kBlock) void pwave_terms_kernel(const PrecomputeArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  const T cl = load_global(static_cast<const T*>(a.in[0]) + i);
+  const T ck = load_global(static_cast<const T*>(a.in[1]) + i);
+  const T ph = load_global(static_cast<const T*>(a.in[2]) + i);
+  T u0, m[8];
+  pwave_terms(cl, ck, ph, u0, m);
+  static_cast<T*>(a.out[0])[i] = u0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) static_cast<T*>(a.out[1 + k])[i] = m[k];
+}
+
+void launch_pwave_terms(const PrecomputeArgs& a, int precision, hipStream_t s) {
+  const unsigned blocks = unsigned((a.n + kBlock - 1) / kBlock);
+  if (precision == UML_MIXED)
+    hipLaunchKernelGGL(pwave_terms_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(pwave_terms_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, a);
 }
 
 const Family* find_family(const std::string& sig) {

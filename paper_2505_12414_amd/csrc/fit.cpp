@@ -45,61 +45,95 @@ size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles) {
 
 int hess_sums(const uml_model* m) { return 1 + m->plan.nfree + 2 * m->hplan.npairs; }
 
+// Events staged at once by the Hessian pass: as many as LDS allows, up to
+// one per thread (0 if even one event does not fit).
+static int hess_chunk(const uml_model* m) {
+  const Plan& P = m->plan;
+  const int row = hess_row_len(P, m->hplan);
+  const size_t fixed = hess_lds_bytes(row, 0, P.precision);
+  const size_t esz = P.precision == UML_MIXED ? 4 : 8;
+  int chunk = kBlock;
+  while (chunk > 1 && fixed + size_t(row) * chunk * esz > 60 * 1024) chunk /= 2;
+  return fixed + size_t(row) * chunk * esz > 64 * 1024 ? 0 : chunk;
+}
+
+// Arguments of the Hessian pass of dataset d at the device parameter vector
+// d_theta; its sums go to d_out, or to the dataset's workspace if d_out is
+// null.
+static int hess_job(const uml_model* m, const uml_data* d, const double* d_theta, double* d_out,
+                    HessJob& J, const char* fn) {
+  if (!m || !d || !d_theta) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+  if (d->model != m)
+    return set_error(UML_E_INVALID, std::string(fn) + ": data was created for another model");
+  if (!m->d_hplan)
+    return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": " + m->hess_err);
+  const Plan& P = m->plan;
+  const HessLayout HL = hess_layout(m, d->n);
+  const int chunk = hess_chunk(m);
+  if (!chunk) return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": model too large for the Hessian pass");
+  if (!d->d_hwork || d->hess_tiles != HL.n_tiles)
+    return set_error(UML_E_INVALID, std::string(fn) + ": missing Hessian workspace");
+  char* base = static_cast<char*>(d->d_hwork);
+  HessArgs& A = J.A;
+  A = HessArgs{};
+  for (int k = 0; k < P.ndim; ++k) A.col[k] = d->job.col[k];
+  A.w = d->job.w;
+  A.n = d->n;
+  A.plan = m->d_plan;
+  A.cb = reinterpret_cast<ConstBlock*>(base + HL.o_cb);
+  A.hc = reinterpret_cast<double*>(base + HL.o_hc);
+  A.hplan = m->d_hplan;
+  A.part = reinterpret_cast<double*>(base + HL.o_part);
+  A.n_tiles = HL.n_tiles;
+  A.tile_events = hess_tile_events(d->n);
+  A.chunk = chunk;
+  A.row_len = hess_row_len(P, m->hplan);
+  A.n_sums = HL.M;
+  J.theta = d_theta;
+  J.out = d_out ? d_out : reinterpret_cast<double*>(base + HL.o_out);
+  return UML_OK;
+}
+
 // Queues the Hessian pass at the device parameter vector d_theta on stream s;
 // the raw sums [sum w log2 P, sum w s (nfree), H pairs, W2 pairs] are copied
 // to h_out (host; pinned memory keeps the call asynchronous) when the stream
 // gets there.
 int hessian_queue(const uml_model* m, uml_data* d, const double* d_theta, double* h_out,
                   hipStream_t s, const char* fn) {
-  if (!m || !d || !d_theta || !h_out) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
-  if (d->model != m)
-    return set_error(UML_E_INVALID, std::string(fn) + ": data was created for another model");
-  if (!m->d_hplan)
-    return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": " + m->hess_err);
-  const Plan& P = m->plan;
-  const int row = hess_row_len(P, m->hplan);
-  const HessLayout HL = hess_layout(m, d->n);
-  const int M = HL.M;
-  const int n_tiles = HL.n_tiles;
-  const size_t fixed = hess_lds_bytes(row, 0, P.precision);
-  const size_t esz = P.precision == UML_MIXED ? 4 : 8;
-  int chunk = kBlock;  // events staged at once: as many as LDS allows, up to one per thread
-  while (chunk > 1 && fixed + size_t(row) * chunk * esz > 60 * 1024) chunk /= 2;
-  if (fixed + size_t(row) * chunk * esz > 64 * 1024)
-    return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": model too large for the Hessian pass");
-  const size_t o_cb = HL.o_cb, o_hc = HL.o_hc, o_out = HL.o_out, o_part = HL.o_part;
-  if (!d->d_hwork || d->hess_tiles != n_tiles) {
-    if (!d->owns_memory)
-      return set_error(UML_E_INVALID, std::string(fn) + ": missing Hessian workspace");
-    if (d->d_hwork) (void)hipFree(d->d_hwork);
-    d->d_hwork = nullptr;
-    hipError_t e = hipMalloc(&d->d_hwork, HL.bytes);
-    if (e != hipSuccess) {
-      d->d_hwork = nullptr;
-      return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
-    }
-    d->hess_tiles = n_tiles;
-  }
-  char* base = static_cast<char*>(d->d_hwork);
-  HessArgs A{};
-  for (int k = 0; k < P.ndim; ++k) A.col[k] = d->job.col[k];
-  A.w = d->job.w;
-  A.n = d->n;
-  A.plan = m->d_plan;
-  A.cb = reinterpret_cast<ConstBlock*>(base + o_cb);
-  A.hc = reinterpret_cast<double*>(base + o_hc);
-  A.hplan = m->d_hplan;
-  A.part = reinterpret_cast<double*>(base + o_part);
-  A.n_tiles = n_tiles;
-  A.tile_events = hess_tile_events(d->n);
-  A.chunk = chunk;
-  A.row_len = row;
-  A.n_sums = M;
-  launch_hessian(A, d_theta, reinterpret_cast<ConstBlock*>(base + o_cb),
-                 reinterpret_cast<double*>(base + o_hc), reinterpret_cast<double*>(base + o_out),
-                 P.precision, s);
+  if (!h_out) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+  HessJob J;
+  int rc = hess_job(m, d, d_theta, nullptr, J, fn);
+  if (rc != UML_OK) return rc;
+  launch_hessian(J.A, d_theta, const_cast<ConstBlock*>(J.A.cb), const_cast<double*>(J.A.hc), J.out,
+                 m->plan.precision, s);
   UML_HIP_CHECK(hipGetLastError());
-  UML_HIP_CHECK(hipMemcpyAsync(h_out, base + o_out, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+  UML_HIP_CHECK(hipMemcpyAsync(h_out, J.out, sizeof(double) * J.A.n_sums, hipMemcpyDeviceToHost, s));
+  return UML_OK;
+}
+
+// Queues one Hessian pass over n datasets of model m (batched launches):
+// dataset i at the device parameter vector d_thetas[i], its sums to
+// d_outs + i * hess_sums(m).  The job table and tile map are staged through
+// h_jobs / h_map (host, pinned, capacity n and map_cap) into d_jobs / d_map.
+int hessian_queue_batch(const uml_model* m, uml_data* const* ds, const double* const* d_thetas, int n,
+                        double* d_outs, HessJob* h_jobs, HessJob* d_jobs, int2* h_map, int2* d_map,
+                        int map_cap, hipStream_t s, const char* fn) {
+  if (n <= 0) return UML_OK;
+  const int M = hess_sums(m);
+  int n_map = 0;
+  for (int i = 0; i < n; ++i) {
+    int rc = hess_job(m, ds[i], d_thetas[i], d_outs + size_t(i) * M, h_jobs[i], fn);
+    if (rc != UML_OK) return rc;
+    for (int t = 0; t < h_jobs[i].A.n_tiles; ++t) {
+      if (n_map >= map_cap) return set_error(UML_E_INVALID, std::string(fn) + ": Hessian tile map full");
+      h_map[n_map++] = make_int2(i, t);
+    }
+  }
+  UML_HIP_CHECK(hipMemcpyAsync(d_jobs, h_jobs, sizeof(HessJob) * n, hipMemcpyHostToDevice, s));
+  UML_HIP_CHECK(hipMemcpyAsync(d_map, h_map, sizeof(int2) * n_map, hipMemcpyHostToDevice, s));
+  launch_hessian_batch(d_jobs, n, d_map, n_map, h_jobs[0].A.row_len, h_jobs[0].A.chunk, M,
+                       m->plan.precision, s);
+  UML_HIP_CHECK(hipGetLastError());
   return UML_OK;
 }
 

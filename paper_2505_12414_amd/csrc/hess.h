@@ -45,6 +45,14 @@ struct HessArgs {
   int n_sums;              // 1 + nfree + 2 npairs
 };
 
+// One dataset of a batched Hessian pass: its arguments, its parameter vector
+// (device) and where its M sums go (device).
+struct HessJob {
+  HessArgs A;
+  const double* theta;
+  double* out;
+};
+
 // Builds the Hessian structure; returns false (with a message) when a
 // parameter appears in two units of one component.
 bool build_hess_plan(const Plan& P, HessPlan& H, std::string& err);
@@ -52,5 +60,10 @@ int hess_row_len(const Plan& P, const HessPlan& H);
 size_t hess_lds_bytes(int row_len, int chunk, int precision);
 void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, double* d_hc,
                     double* d_out, int precision, hipStream_t s);
+// Batched pass over n_jobs datasets of one model: d_map holds n_map (job,
+// tile) entries (job < 0: padding); row_len, chunk and n_sums are the
+// model's.
+void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, int n_map, int row_len,
+                          int chunk, int n_sums, int precision, hipStream_t s);
 
 }  // namespace uml

@@ -75,6 +75,14 @@ __global__ __launch_bounds__(64) void hess_prologue_kernel(const Plan* __restric
   hess_constants(*plan, theta, hc);
 }
 
+// The same for a batch: workgroup j prepares job j.
+__global__ __launch_bounds__(64) void hess_prologue_batch_kernel(const HessJob* __restrict__ jobs) {
+  if (threadIdx.x != 0) return;
+  const HessJob& J = jobs[blockIdx.x];
+  compute_constants(*J.A.plan, J.theta, const_cast<ConstBlock*>(J.A.cb));
+  hess_constants(*J.A.plan, J.theta, const_cast<double*>(J.A.hc));
+}
+
 template <class T>
 __device__ __forceinline__ T ld(const void* col, int64_t i) {
   return static_cast<const T*>(col)[i];
@@ -204,8 +212,9 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
   }
 }
 
+// One tile of one dataset: its M sums go to A.part[j * A.n_tiles + tile].
 template <class T>
-__global__ __launch_bounds__(kBlock) void hess_kernel(const HessArgs A) {
+__device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   Plan* sP = reinterpret_cast<Plan*>(lds_raw);
   ConstBlock* sC = reinterpret_cast<ConstBlock*>(lds_raw + sizeof(Plan));
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void hess_kernel(const HessArgs A) {
   const int nf = P.nfree, nc = P.ncomp, V = A.row_len, M = A.n_sums;
   double acc[kHessSumsPerThread];
   for (int k = 0; k < kHessSumsPerThread; ++k) acc[k] = 0.0;
-  const int64_t t0 = int64_t(blockIdx.x) * A.tile_events;
+  const int64_t t0 = int64_t(tile) * A.tile_events;
   const int64_t t1 = t0 + A.tile_events < A.n ? t0 + A.tile_events : A.n;
   for (int64_t c0 = t0; c0 < t1; c0 += A.chunk) {
     const int cnt = int((t1 - c0) < A.chunk ? (t1 - c0) : A.chunk);
@@ -280,15 +289,29 @@ __global__ __launch_bounds__(kBlock) void hess_kernel(const HessArgs A) {
   }
   for (int k = 0; k < kHessSumsPerThread; ++k) {
     const int j = tid + k * kBlock;
-    if (j < M) A.part[int64_t(j) * gridDim.x + blockIdx.x] = acc[k];
+    if (j < M) A.part[int64_t(j) * A.n_tiles + tile] = acc[k];
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(kBlock) void hess_kernel(const HessArgs A) {
+  hess_tile<T>(A, blockIdx.x);
+}
+
+// A batch: the ragged map names (job, tile) for each workgroup; entries with
+// a negative job are padding.
+template <class T>
+__global__ __launch_bounds__(kBlock) void hess_batch_kernel(const HessJob* __restrict__ jobs,
+                                                            const int2* __restrict__ tmap) {
+  const int2 t = tmap[blockIdx.x];
+  if (t.x < 0) return;
+  const HessArgs A = jobs[t.x].A;
+  hess_tile<T>(A, t.y);
+}
+
 // Sum j of every tile, in tile order (Neumaier).
-__global__ __launch_bounds__(kBlock) void hess_reduce_kernel(const double* __restrict__ part, int n_tiles,
-                                                             int M, double* __restrict__ out) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= M) return;
+__device__ __forceinline__ void hess_reduce(const double* __restrict__ part, int n_tiles, int j,
+                                            double* __restrict__ out) {
   const double* col = part + int64_t(j) * n_tiles;
   double s = 0.0, comp = 0.0;
   for (int t = 0; t < n_tiles; ++t) {
@@ -298,6 +321,19 @@ __global__ __launch_bounds__(kBlock) void hess_reduce_kernel(const double* __res
     s = u;
   }
   out[j] = s + comp;
+}
+
+__global__ __launch_bounds__(kBlock) void hess_reduce_kernel(const double* __restrict__ part, int n_tiles,
+                                                             int M, double* __restrict__ out) {
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < M) hess_reduce(part, n_tiles, j, out);
+}
+
+// A batch: blockIdx.y is the job.
+__global__ __launch_bounds__(kBlock) void hess_reduce_batch_kernel(const HessJob* __restrict__ jobs) {
+  const HessJob& J = jobs[blockIdx.y];
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < J.A.n_sums) hess_reduce(J.A.part, J.A.n_tiles, j, J.out);
 }
 
 size_t hess_lds_bytes(int row_len, int chunk, int precision) {
@@ -315,6 +351,19 @@ void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, 
     hipLaunchKernelGGL(hess_kernel<double>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
   hipLaunchKernelGGL(hess_reduce_kernel, dim3((A.n_sums + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                      A.part, A.n_tiles, A.n_sums, d_out);
+}
+
+void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, int n_map, int row_len,
+                          int chunk, int n_sums, int precision, hipStream_t s) {
+  if (n_jobs <= 0) return;
+  hipLaunchKernelGGL(hess_prologue_batch_kernel, dim3(n_jobs), dim3(64), 0, s, d_jobs);
+  const size_t lds = hess_lds_bytes(row_len, chunk, precision);
+  if (precision == UML_MIXED)
+    hipLaunchKernelGGL(hess_batch_kernel<float>, dim3(n_map), dim3(kBlock), lds, s, d_jobs, d_map);
+  else
+    hipLaunchKernelGGL(hess_batch_kernel<double>, dim3(n_map), dim3(kBlock), lds, s, d_jobs, d_map);
+  hipLaunchKernelGGL(hess_reduce_batch_kernel, dim3((n_sums + kBlock - 1) / kBlock, n_jobs), dim3(kBlock), 0,
+                     s, d_jobs);
 }
 
 }  // namespace uml

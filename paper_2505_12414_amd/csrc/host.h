@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "gen.h"
 #include "hess.h"
 #include "kernels.h"
 #include "uml_internal.h"
@@ -23,6 +24,8 @@ struct uml_model {
   // grown on demand and kept until the model is destroyed
   mutable void* d_fitws = nullptr;
   mutable size_t fitws_bytes = 0;
+  uml::GenPlan gplan;                // the model tree for generation
+  uml::GenPlan* d_gplan = nullptr;   // device copy
 };
 
 struct uml_data {
@@ -68,6 +71,9 @@ DataLayout data_layout(const Plan& P, int64_t n, bool weighted);
 void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const DataLayout& L,
                void* d_events, void* d_work);
 hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s);
+hipError_t data_init_work(uml_data* d, const DataLayout& L, hipStream_t s);
+int check_generation_theta(const uml_model* m, const double* theta, const char* fn);
+GenOut gen_out(const uml_data* d, unsigned int* d_bad);
 size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles);
 double* pinned_stage_get();
 void pinned_stage_put(double* p);
@@ -75,6 +81,9 @@ void pinned_stage_put(double* p);
 int hess_sums(const uml_model* m);
 int hessian_queue(const uml_model* m, uml_data* d, const double* d_theta, double* h_out,
                   hipStream_t s, const char* fn);
+int hessian_queue_batch(const uml_model* m, uml_data* const* ds, const double* const* d_thetas, int n,
+                        double* d_outs, HessJob* h_jobs, HessJob* d_jobs, int2* h_map, int2* d_map,
+                        int map_cap, hipStream_t s, const char* fn);
 int hessian_host(const uml_model* m, uml_data* d, const double* theta, hipStream_t s,
                  std::vector<double>& out, const char* fn);
 int unpack_hessian(const uml_model* m, const double* h, double* nll, double* grad, double* hess,

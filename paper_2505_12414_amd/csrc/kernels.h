@@ -20,6 +20,15 @@ struct LaunchArgs {
 };
 
 // One compiled model shape: its signature (see plan_signature) and launchers.
+// The precomputed P-wave terms of a dataset: angle columns in, nine columns
+// out (u0 and the eight angular terms), in the storage type.
+struct PrecomputeArgs {
+  const void* in[3];
+  void* out[kPWaveTerms];
+  int64_t n;
+};
+void launch_pwave_terms(const PrecomputeArgs& a, int precision, hipStream_t s);
+
 struct Family {
   std::string sig;
   int K;       // accumulators per event

@@ -94,10 +94,13 @@ std::string plan_signature(const Plan& P) {
     if (c) s += "|";
     for (int j = 0; j < P.comp[c].nfac; ++j) {
       const FactorPlan& F = P.fac[P.comp[c].fac[j]];
-      s += kind_letter(F.kind);
-      if (F.kind == FK_PWAVE) {
+      if (F.kind == FK_PWAVE && F.pre >= 0) {  // terms read from columns pre .. pre + 8
+        s += "Q" + std::to_string(F.pre);
+      } else if (F.kind == FK_PWAVE) {
+        s += kind_letter(F.kind);
         for (int k = 0; k < 3; ++k) s += std::to_string(F.dim[k]);
       } else {
+        s += kind_letter(F.kind);
         s += std::to_string(F.dim[0]);
         if (F.kind == FK_CHEB) s += "." + std::to_string(F.order);
       }
@@ -331,6 +334,7 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
       }
       for (int k = 0; k < nd.n_params; ++k) F.par[k] = nd.params[k];
       F.xref = P.xref[F.dim[0]];
+      F.pre = -1;
       F.cst = cst;
       F.ecst = ecst;
       F.mom = mom;
@@ -393,6 +397,33 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
     }
   }
   P.precision = d->precision;
+  // stored columns: the dimensions, then the precomputed P-wave terms
+  P.ncol = P.ndim;
+  P.pre_fac = -1;
+  if (d->flags & ~UML_MODEL_PRECOMPUTE_ANGULAR) {
+    err = "unknown model flags";
+    return UML_E_INVALID;
+  }
+  if (d->flags & UML_MODEL_PRECOMPUTE_ANGULAR) {
+    for (int f = 0; f < P.nfac; ++f) {
+      if (P.fac[f].kind != FK_PWAVE) continue;
+      if (P.pre_fac >= 0) {
+        err = "precomputed angular terms need a model with one P-wave factor";
+        return UML_E_UNSUPPORTED;
+      }
+      P.pre_fac = f;
+      P.fac[f].pre = P.ncol;
+      P.ncol += kPWaveTerms;
+    }
+    if (P.pre_fac < 0) {
+      err = "precomputed angular terms need a P-wave factor";
+      return UML_E_INVALID;
+    }
+    if (P.ncol > kMaxCols) {
+      err = "too many stored columns";
+      return UML_E_UNSUPPORTED;
+    }
+  }
   return UML_OK;
 }
 

@@ -91,6 +91,9 @@ struct Request {
   uint64_t ticket = 0;
   int64_t n = 0;
   bool weighted = false;
+  bool generate = false;      // events drawn on the device (seed, gen_theta)
+  uint64_t seed = 0;
+  std::vector<double> gen_theta;
   std::vector<char> host;     // converted event storage (kernel order)
   std::vector<double> start;  // all parameters
   size_t bytes = 0;           // arena footprint
@@ -106,13 +109,13 @@ struct Slot {
   size_t o_work = 0, o_hess = 0;
 };
 
-// Pinned host staging of one slot: the start point going up, the fit state
-// and the Hessian-pass sums coming down.  Pinned, so that the copies of a
-// whole batch of slots are queued together and waited for once.
+// Pinned host staging of one slot: the start point (and the point events are
+// drawn at) going up, the fit state coming down.  Pinned, so that the copies
+// of a whole batch of slots are queued together and waited for once.
 struct SlotHost {
   FitState fs;
   double theta[UML_MAX_PARAMS];
-  double sums[1 + UML_MAX_PARAMS + UML_MAX_PARAMS * (UML_MAX_PARAMS + 1)];
+  double gen_theta[UML_MAX_PARAMS];
 };
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
@@ -148,6 +151,7 @@ struct uml_server {
   uint64_t next_ticket = 1;
   int64_t submitted = 0, admitted = 0, finished = 0, iterations = 0;
   int64_t resident = 0, peak_resident = 0, budget_waits = 0;  // arena bytes in use
+  double t_admit = 0.0, t_iterate = 0.0, t_retire = 0.0;     // worker phase times
   int active = 0;
   bool stop = false;
   int worker_error = 0;
@@ -164,6 +168,21 @@ struct uml_server {
   int map_cap = 0;
   SlotHost* h_slots = nullptr;  // pinned, one per slot
   int* h_done = nullptr;        // pinned, one per slot
+  // batched Hessian passes: job tables, tile map, sums (pinned and device)
+  HessJob* h_hjobs = nullptr;
+  HessJob* d_hjobs = nullptr;
+  int2* h_hmap = nullptr;
+  int2* d_hmap = nullptr;
+  int hmap_cap = 0;
+  double* h_hsums = nullptr;
+  double* d_hsums = nullptr;
+  unsigned int* d_genbad = nullptr;  // per slot: events that failed to draw
+  unsigned int* h_genbad = nullptr;
+  // batched generation: job table and block map (pinned and device)
+  GenJob* h_genjobs = nullptr;
+  GenJob* d_genjobs = nullptr;
+  int2* h_genmap = nullptr;
+  int2* d_genmap = nullptr;
   std::vector<Slot> slots;
   std::vector<Job> jobs;
   std::map<int, CapturedGraph> graphs;  // by grid bucket
@@ -217,6 +236,9 @@ struct Intake {
 // request whose start point has P <= 0 somewhere is answered at once.
 int admit_batch(uml_server* S, std::vector<Intake>& in) {
   const uml_model* m = S->m;
+  const int ns = int(S->slots.size());
+  UML_HIP_CHECK(hipMemsetAsync(S->d_genbad, 0, sizeof(unsigned int) * ns, S->stream));
+  int n_gen = 0, n_gmap = 0;  // requests drawn on the device, in one batched launch
   for (auto& it : in) {
     Slot& sl = S->slots[it.slot];
     sl.off = it.off;
@@ -232,23 +254,76 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     hess_work_bytes(m, sl.req.n, &sl.data.hess_tiles);
     sl.data.h_stage = S->h_slots[it.slot].theta;
     sl.data.owns_memory = 0;
-    hipError_t e = data_upload(&sl.data, sl.layout, sl.req.host, S->stream);
+    SlotHost& H = S->h_slots[it.slot];
+    hipError_t e = hipSuccess;
+    if (sl.req.generate) {  // drawn below; until then the output area holds the point
+      std::memcpy(H.gen_theta, sl.req.gen_theta.data(), sizeof(double) * m->plan.npar);
+      e = hipMemcpyAsync(sl.data.d_out, H.gen_theta, sizeof(double) * m->plan.npar, hipMemcpyHostToDevice,
+                         S->stream);
+      S->h_genjobs[n_gen] = GenJob{gen_out(&sl.data, S->d_genbad + it.slot), sl.data.d_out, sl.req.seed};
+      for (int64_t b = 0; b * 256 < sl.req.n; ++b) {
+        if (n_gmap >= S->hmap_cap) return set_error(UML_E_INVALID, "server: generation map full");
+        S->h_genmap[n_gmap++] = make_int2(n_gen, int(b));
+      }
+      ++n_gen;
+    } else {
+      e = data_upload(&sl.data, sl.layout, sl.req.host, S->stream);
+    }
     if (e != hipSuccess) return set_error(UML_E_HIP, std::string("server upload: ") + hipGetErrorString(e));
+  }
+  if (n_gen) {  // one launch draws every generated request; then their work areas
+    UML_HIP_CHECK(hipMemcpyAsync(S->d_genjobs, S->h_genjobs, sizeof(GenJob) * n_gen, hipMemcpyHostToDevice,
+                                 S->stream));
+    UML_HIP_CHECK(hipMemcpyAsync(S->d_genmap, S->h_genmap, sizeof(int2) * n_gmap, hipMemcpyHostToDevice,
+                                 S->stream));
+    launch_generate_batch(m->d_gplan, S->d_genjobs, S->d_genmap, n_gmap, m->plan.precision, S->stream);
+    UML_HIP_CHECK(hipGetLastError());
+    for (auto& it : in) {
+      Slot& sl = S->slots[it.slot];
+      if (sl.req.generate) UML_HIP_CHECK(data_init_work(&sl.data, sl.layout, S->stream));
+    }
+  }
+  // start points, once every work area is initialised (which clears them)
+  for (auto& it : in) {
+    Slot& sl = S->slots[it.slot];
     SlotHost& H = S->h_slots[it.slot];
     std::memcpy(H.theta, sl.req.start.data(), sizeof(double) * m->plan.npar);
     UML_HIP_CHECK(hipMemcpyAsync(sl.data.d_theta, H.theta, sizeof(double) * m->plan.npar,
                                  hipMemcpyHostToDevice, S->stream));
-    int rc = hessian_queue(m, &sl.data, sl.data.d_theta, H.sums, S->stream, "server");
-    if (rc != UML_OK) return rc;
   }
+  const int nb = int(in.size()), M = hess_sums(m);
+  std::vector<uml_data*> ds(nb);
+  std::vector<const double*> th(nb);
+  for (int j = 0; j < nb; ++j) {
+    ds[j] = &S->slots[in[j].slot].data;
+    th[j] = ds[j]->d_theta;
+  }
+  int rc = hessian_queue_batch(m, ds.data(), th.data(), nb, S->d_hsums, S->h_hjobs, S->d_hjobs, S->h_hmap,
+                               S->d_hmap, S->hmap_cap, S->stream, "server");
+  if (rc != UML_OK) return rc;
+  UML_HIP_CHECK(hipMemcpyAsync(S->h_hsums, S->d_hsums, sizeof(double) * nb * M, hipMemcpyDeviceToHost,
+                               S->stream));
+  UML_HIP_CHECK(hipMemcpyAsync(S->h_genbad, S->d_genbad, sizeof(unsigned int) * ns, hipMemcpyDeviceToHost,
+                               S->stream));
   UML_HIP_CHECK(hipStreamSynchronize(S->stream));
-  for (auto& it : in) {
-    const int i = it.slot;
+  for (int j = 0; j < nb; ++j) {
+    const int i = in[j].slot;
     Slot& sl = S->slots[i];
     SlotHost& H = S->h_slots[i];
     std::vector<char>().swap(sl.req.host);  // uploaded
+    if (sl.req.generate && S->h_genbad[i]) {  // some events could not be drawn
+      uml_fit_result r;
+      std::memset(&r, 0, sizeof(r));
+      r.n_free = m->plan.nfree;
+      r.status = UML_FIT_GENERATION_FAILED;
+      r.nll = INFINITY;
+      for (int k = 0; k < m->plan.npar; ++k) r.params[k] = sl.req.start[k];
+      release_slot(S, sl);
+      push_result(S, r, sl.req);
+      continue;
+    }
     fit_state_begin(m, sl.req.start.data(), S->opt.fit, H.fs);
-    int rc = fit_state_metric(m, H.sums, H.fs, "server");
+    rc = fit_state_metric(m, S->h_hsums + size_t(j) * M, H.fs, "server");
     if (rc != UML_OK) return rc;
     if (H.fs.done) {  // P <= 0 at the start point
       uml_fit_result r;
@@ -282,16 +357,26 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
   const uml_model* m = S->m;
   const Plan& P = m->plan;
   const bool polish = S->opt.fit.polish > 0;
-  for (int i : fin) {
-    SlotHost& H = S->h_slots[i];
-    UML_HIP_CHECK(hipMemcpyAsync(&H.fs, S->d_fs + i, sizeof(FitState), hipMemcpyDeviceToHost, S->stream));
-    if (!polish) {
-      int rc = hessian_queue(m, &S->slots[i].data, S->d_fs[i].theta, H.sums, S->stream, "server");
-      if (rc != UML_OK) return rc;
+  const int nb = int(fin.size()), M = hess_sums(m);
+  for (int i : fin)
+    UML_HIP_CHECK(hipMemcpyAsync(&S->h_slots[i].fs, S->d_fs + i, sizeof(FitState), hipMemcpyDeviceToHost,
+                                 S->stream));
+  if (!polish) {  // the Hessian pass at each final point, read on the device
+    std::vector<uml_data*> ds(nb);
+    std::vector<const double*> th(nb);
+    for (int j = 0; j < nb; ++j) {
+      ds[j] = &S->slots[fin[j]].data;
+      th[j] = S->d_fs[fin[j]].theta;
     }
+    int rc = hessian_queue_batch(m, ds.data(), th.data(), nb, S->d_hsums, S->h_hjobs, S->d_hjobs,
+                                 S->h_hmap, S->d_hmap, S->hmap_cap, S->stream, "server");
+    if (rc != UML_OK) return rc;
+    UML_HIP_CHECK(hipMemcpyAsync(S->h_hsums, S->d_hsums, sizeof(double) * nb * M, hipMemcpyDeviceToHost,
+                                 S->stream));
   }
   UML_HIP_CHECK(hipStreamSynchronize(S->stream));
-  for (int i : fin) {
+  for (int j = 0; j < nb; ++j) {
+    const int i = fin[j];
     Slot& sl = S->slots[i];
     const FitState& F = S->h_slots[i].fs;
     uml_fit_result r;
@@ -304,7 +389,7 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
       for (int k = 0; k < P.npar; ++k) r.params[k] = F.theta[k];
       r.nll = INFINITY;
     } else if (!polish) {
-      finish_from_sums(m, S->h_slots[i].sums, F.theta, S->opt.fit, &r, "server");
+      finish_from_sums(m, S->h_hsums + size_t(j) * M, F.theta, S->opt.fit, &r, "server");
     } else {
       std::vector<double> theta(F.theta, F.theta + P.npar);
       int rc = finish_fit(m, &sl.data, theta, S->opt.fit, &r, S->stream, "server");
@@ -347,6 +432,18 @@ int graph_for(uml_server* S, int bucket, hipGraphExec_t* exec) {
   return UML_OK;
 }
 
+// Device and pinned memory and the stream of a server (what was allocated).
+void free_server_memory(uml_server* S) {
+  if (S->arena_mem) (void)hipFree(S->arena_mem);
+  if (S->state_mem) (void)hipFree(S->state_mem);
+  for (void* p : {static_cast<void*>(S->h_slots), static_cast<void*>(S->h_done),
+                  static_cast<void*>(S->h_hjobs), static_cast<void*>(S->h_hmap),
+                  static_cast<void*>(S->h_hsums), static_cast<void*>(S->h_genbad),
+                  static_cast<void*>(S->h_genjobs), static_cast<void*>(S->h_genmap)})
+    if (p) (void)hipHostFree(p);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+}
+
 void worker_main(uml_server* S) {
   (void)hipSetDevice(S->m->device);
   const int ns = int(S->slots.size());
@@ -380,7 +477,12 @@ void worker_main(uml_server* S) {
       S->admitted += int64_t(intake.size());
     }
     if (!intake.empty()) {
+      const double t0 = now_s();
       int rc = admit_batch(S, intake);
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->t_admit += now_s() - t0;
+      }
       if (rc != UML_OK) {
         fail_worker(S, rc, uml_last_error());
         return;
@@ -407,6 +509,7 @@ void worker_main(uml_server* S) {
       }
       dirty = false;
     }
+    const double t_it = now_s();
     hipGraphExec_t exec = nullptr;
     int rc = graph_for(S, bucket, &exec);
     if (rc != UML_OK) {
@@ -425,12 +528,18 @@ void worker_main(uml_server* S) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->iterations += kItersPerReplay;
+      S->t_iterate += now_s() - t_it;
     }
     fin.clear();
     for (int i = 0; i < ns; ++i)
       if (S->slots[i].used && S->h_done[i]) fin.push_back(i);
     if (!fin.empty()) {
+      const double t0 = now_s();
       rc = retire_batch(S, fin);
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->t_retire += now_s() - t0;
+      }
       if (rc != UML_OK) {
         fail_worker(S, rc, uml_last_error());
         return;
@@ -480,12 +589,13 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   const int64_t tile_bytes = int64_t(one.E) * kBlock * (m->plan.precision == UML_MIXED ? 4 : 8);
   S->map_cap = grid_bucket(
       int(std::min<int64_t>(S->opt.hbm_budget / std::max<int64_t>(tile_bytes, 1) + ns, 1 << 22)));
+  // Hessian tile map capacity: a request has at most n / 256 + 1 Hessian
+  // tiles, and the arena holds at most budget / (bytes per event) events
+  const int64_t ev_bytes = int64_t(m->plan.ndim) * (m->plan.precision == UML_MIXED ? 4 : 8);
+  S->hmap_cap = int(std::min<int64_t>(S->opt.hbm_budget / (256 * ev_bytes) + ns, 1 << 22));
+  const int M = hess_sums(m);
   auto fail = [&](hipError_t e, const char* what) {
-    if (S->arena_mem) (void)hipFree(S->arena_mem);
-    if (S->state_mem) (void)hipFree(S->state_mem);
-    if (S->h_slots) (void)hipHostFree(S->h_slots);
-    if (S->h_done) (void)hipHostFree(S->h_done);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
+    free_server_memory(S);
     delete S;
     return set_error(e == hipErrorOutOfMemory ? UML_E_NOMEM : UML_E_HIP,
                      std::string("uml_server_create: ") + what + ": " + hipGetErrorString(e));
@@ -496,18 +606,46 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   e = hipMalloc(&S->arena_mem, size_t(S->opt.hbm_budget));
   if (e != hipSuccess) return fail(e, "arena");
   const size_t o_jobs = round256(sizeof(FitState) * ns), o_map = o_jobs + round256(sizeof(Job) * ns);
-  e = hipMalloc(&S->state_mem, o_map + sizeof(int2) * size_t(S->map_cap));
+  const size_t o_hjobs = o_map + round256(sizeof(int2) * size_t(S->map_cap));
+  const size_t o_hmap = o_hjobs + round256(sizeof(HessJob) * ns);
+  const size_t o_hsums = o_hmap + round256(sizeof(int2) * size_t(S->hmap_cap));
+  const size_t o_genbad = o_hsums + round256(sizeof(double) * size_t(ns) * M);
+  const size_t o_genjobs = o_genbad + round256(sizeof(unsigned int) * ns);
+  const size_t o_genmap = o_genjobs + round256(sizeof(GenJob) * ns);
+  e = hipMalloc(&S->state_mem, o_genmap + sizeof(int2) * size_t(S->hmap_cap));
   if (e != hipSuccess) return fail(e, "fit states");
   e = hipMemset(S->state_mem, 0, o_map);
   if (e != hipSuccess) return fail(e, "fit states");
   e = hipHostMalloc(reinterpret_cast<void**>(&S->h_slots), sizeof(SlotHost) * ns, hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&S->h_done), sizeof(int) * ns, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hjobs), sizeof(HessJob) * ns, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hmap), sizeof(int2) * size_t(S->hmap_cap),
+                      hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hsums), sizeof(double) * size_t(ns) * M,
+                      hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genbad), sizeof(unsigned int) * ns,
+                      hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genjobs), sizeof(GenJob) * ns, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genmap), sizeof(int2) * size_t(S->hmap_cap),
+                      hipHostMallocDefault);
   if (e != hipSuccess) return fail(e, "pinned staging");
   S->arena.init(static_cast<char*>(S->arena_mem), size_t(S->opt.hbm_budget));
   S->d_fs = reinterpret_cast<FitState*>(S->state_mem);
   S->d_jobs = reinterpret_cast<Job*>(static_cast<char*>(S->state_mem) + o_jobs);
   S->d_map = reinterpret_cast<int2*>(static_cast<char*>(S->state_mem) + o_map);
+  S->d_hjobs = reinterpret_cast<HessJob*>(static_cast<char*>(S->state_mem) + o_hjobs);
+  S->d_hmap = reinterpret_cast<int2*>(static_cast<char*>(S->state_mem) + o_hmap);
+  S->d_hsums = reinterpret_cast<double*>(static_cast<char*>(S->state_mem) + o_hsums);
+  S->d_genbad = reinterpret_cast<unsigned int*>(static_cast<char*>(S->state_mem) + o_genbad);
+  S->d_genjobs = reinterpret_cast<GenJob*>(static_cast<char*>(S->state_mem) + o_genjobs);
+  S->d_genmap = reinterpret_cast<int2*>(static_cast<char*>(S->state_mem) + o_genmap);
   // idle slots read as finished so that their (never mapped) tiles do nothing
   std::vector<FitState> idle(ns);
   for (auto& F : idle) {
@@ -527,9 +665,19 @@ int uml_server_submit(uml_server* S, const uml_request* q, uint64_t* ticket) {
   const Plan& P = S->m->plan;
   Request r;
   r.n = q->n_events;
-  r.weighted = q->w != nullptr;
-  int rc = convert_events(P, q->n_events, q->cols, q->dtype, q->w, r.host, "uml_server_submit");
-  if (rc != UML_OK) return rc;
+  if (q->generate) {
+    if (q->n_events < 0) return set_error(UML_E_INVALID, "uml_server_submit: negative event count");
+    const double* gt = q->gen_theta ? q->gen_theta : S->m->theta0.data();
+    int rc = check_generation_theta(S->m, gt, "uml_server_submit");
+    if (rc != UML_OK) return rc;
+    r.generate = true;
+    r.seed = q->seed;
+    r.gen_theta.assign(gt, gt + P.npar);
+  } else {
+    r.weighted = q->w != nullptr;
+    int rc = convert_events(P, q->n_events, q->cols, q->dtype, q->w, r.host, "uml_server_submit");
+    if (rc != UML_OK) return rc;
+  }
   r.start.resize(P.npar);
   for (int k = 0; k < P.npar; ++k) r.start[k] = q->start ? q->start[k] : S->m->theta0[k];
   r.bytes = request_bytes(S->m, r.n, r.weighted);
@@ -582,6 +730,9 @@ int uml_server_stats_get(uml_server* S, uml_server_stats* st) {
   st->resident_bytes = S->resident;
   st->peak_resident_bytes = S->peak_resident;
   st->budget_waits = S->budget_waits;
+  st->t_admit_s = S->t_admit;
+  st->t_iterate_s = S->t_iterate;
+  st->t_retire_s = S->t_retire;
   return UML_OK;
 }
 
@@ -607,11 +758,7 @@ void uml_server_destroy(uml_server* S) {
     (void)hipGraphExecDestroy(kv.second.exec);
     (void)hipGraphDestroy(kv.second.graph);
   }
-  if (S->arena_mem) (void)hipFree(S->arena_mem);
-  if (S->state_mem) (void)hipFree(S->state_mem);
-  if (S->h_slots) (void)hipHostFree(S->h_slots);
-  if (S->h_done) (void)hipHostFree(S->h_done);
-  if (S->stream) (void)hipStreamDestroy(S->stream);
+  free_server_memory(S);
   delete S;
 }
 

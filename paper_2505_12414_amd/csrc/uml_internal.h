@@ -39,6 +39,8 @@ constexpr int kMaxK = 64;             // accumulators per event
 constexpr int kMaxCst = 128;          // kernel constants
 constexpr int kMaxECst = 128;         // epilogue constants
 constexpr int kMaxCheb = 4;
+constexpr int kMaxCols = 16;          // stored event columns (dimensions + precomputed terms)
+constexpr int kPWaveTerms = 9;        // precomputed P-wave columns: u0 and the 8 angular terms
 
 enum FactorKind { FK_GAUSS = 1, FK_EXP = 2, FK_CHEB = 3, FK_PWAVE = 4 };
 
@@ -66,6 +68,7 @@ struct FactorPlan {
   int mom;           // first moment slot
   double lo[3], hi[3];
   double xref;       // shift of dim[0] (0 if the dimension is not shifted)
+  int pre;           // P-wave: first precomputed column, or -1
 };
 
 struct CompPlan {
@@ -96,6 +99,8 @@ struct Plan {
   int ncst;    // kernel constants
   int necst;   // epilogue constants
   int ndim;    // kernel dimensions
+  int ncol;    // stored columns: the dimensions, then any precomputed terms
+  int pre_fac; // the factor whose terms are precomputed, or -1
   int npar, nfree;
   int free_idx[UML_MAX_PARAMS];  // free position -> parameter
   int free_pos[UML_MAX_PARAMS];  // parameter -> free position or -1
@@ -107,7 +112,7 @@ struct Plan {
   int nterm;
   EpiTerm term[kMaxTerms];              // grouped by parameter
   int term_begin[UML_MAX_PARAMS + 1];   // terms of parameter p: [begin[p], begin[p+1])
-  int pad_[1];
+  int pad_[3];
 };
 static_assert(sizeof(Plan) % 16 == 0, "Plan is copied in 16-byte units");
 
@@ -152,7 +157,7 @@ struct FitState {
 
 // One dataset's share of a launch.
 struct Job {
-  const void* col[UML_MAX_DIMS];  // event columns, kernel-dimension order
+  const void* col[kMaxCols];      // event columns: kernel dimensions, then precomputed terms
   const void* w;                  // weights or nullptr
   int64_t n;                      // events
   int32_t n_tiles;

@@ -32,6 +32,7 @@ UML_E_NOT_PD = -7
 UML_E_BUDGET = -8
 UML_E_QUEUE_FULL = -9
 UML_E_TIMEOUT = -10
+UML_E_GENERATION = -11
 
 UML_FP64, UML_MIXED = 0, 1
 UML_F32, UML_F64 = 0, 1
@@ -40,7 +41,7 @@ MAX_PARAMS = 32
 
 KINDS = {"gauss": 1, "exp": 2, "cheb": 3, "pwave": 4, "prod": 5, "sum": 6}
 FIT_STATUS = {0: "converged", 1: "max_iter", 2: "linesearch_fail", 3: "hessian_not_pd",
-              4: "pdf_nonpositive", 5: "cancelled"}
+              4: "pdf_nonpositive", 5: "cancelled", 6: "generation_failed"}
 
 
 class UmlError(RuntimeError):
@@ -64,11 +65,14 @@ class uml_node(C.Structure):
                 ("children", C.c_int32 * 4)]
 
 
+UML_MODEL_PRECOMPUTE_ANGULAR = 1
+
+
 class uml_model_desc(C.Structure):
     _fields_ = [("n_dims", C.c_int32), ("dims", C.POINTER(uml_dim)),
                 ("n_params", C.c_int32), ("params", C.POINTER(uml_param)),
                 ("n_nodes", C.c_int32), ("nodes", C.POINTER(uml_node)),
-                ("root", C.c_int32), ("precision", C.c_int32)]
+                ("root", C.c_int32), ("precision", C.c_int32), ("flags", C.c_int32)]
 
 
 class uml_fit_options(C.Structure):
@@ -91,14 +95,16 @@ class uml_server_options(C.Structure):
 
 class uml_request(C.Structure):
     _fields_ = [("n_events", C.c_int64), ("cols", C.POINTER(C.c_void_p)), ("dtype", C.c_int32),
-                ("w", C.c_void_p), ("start", C.POINTER(C.c_double))]
+                ("w", C.c_void_p), ("start", C.POINTER(C.c_double)), ("generate", C.c_int32),
+                ("seed", C.c_uint64), ("gen_theta", C.POINTER(C.c_double))]
 
 
 class uml_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("finished", C.c_int64),
                 ("pending", C.c_int64), ("active", C.c_int64), ("iterations", C.c_int64),
                 ("resident_bytes", C.c_int64), ("peak_resident_bytes", C.c_int64),
-                ("budget_waits", C.c_int64)]
+                ("budget_waits", C.c_int64), ("t_admit_s", C.c_double), ("t_iterate_s", C.c_double),
+                ("t_retire_s", C.c_double)]
 
 
 # name -> (restype, argtypes)
@@ -112,6 +118,8 @@ SIGNATURES = {
     "uml_data_create": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_void_p), C.c_int32, _P,
                                   C.c_int32, _P, C.POINTER(_P)]),
     "uml_data_destroy": (None, [_P]),
+    "uml_data_generate": (C.c_int, [_P, C.c_int64, C.c_uint64, _DP, _P, C.POINTER(_P)]),
+    "uml_data_download": (C.c_int, [_P, C.POINTER(C.c_void_p), _P]),
     "uml_data_n_events": (C.c_int64, [_P]),
     "uml_eval_nll": (C.c_int, [_P, _P, _DP, _DP, _P]),
     "uml_eval_nll_grad": (C.c_int, [_P, _P, _DP, _DP, _DP, _P]),
@@ -193,8 +201,11 @@ def _dptr(a):
 class Model:
     """uml_model_create / uml_model_destroy."""
 
-    def __init__(self, desc, precision="mixed"):
+    def __init__(self, desc, precision="mixed", precompute=False):
+        """precompute: store the P-wave's event-only terms as extra columns
+        (UML_MODEL_PRECOMPUTE_ANGULAR) instead of recomputing them."""
         self.desc = desc
+        self.precompute = bool(precompute)
         prec = {"mixed": UML_MIXED, "fp64": UML_FP64}[precision]
         self.precision = precision
         dims = (uml_dim * len(desc["dims"]))(*[uml_dim(d["lo"], d["hi"]) for d in desc["dims"]])
@@ -217,7 +228,7 @@ class Model:
             for k, c in enumerate(ch):
                 n.children[k] = c
         d = uml_model_desc(len(desc["dims"]), dims, len(ps), params, len(desc["nodes"]), nodes,
-                           int(desc["root"]), prec)
+                           int(desc["root"]), prec, UML_MODEL_PRECOMPUTE_ANGULAR if precompute else 0)
         h = _P()
         check(lib().uml_model_create(C.byref(d), C.byref(h)))
         self.handle = h
@@ -290,6 +301,30 @@ class Data:
         self.handle = h
         self.n = n
         self.weighted = weights is not None
+
+    @classmethod
+    def generate(cls, model, n, seed, theta=None, stream=None):
+        """uml_data_generate: a pseudo-experiment of n events drawn on the device
+        from the model at theta (default: the description's values)."""
+        obj = cls.__new__(cls)
+        obj.model = model
+        th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        h = _P()
+        check(lib().uml_data_generate(model.handle, int(n), C.c_uint64(int(seed)),
+                                      None if th is None else _dptr(th), _stream_ptr(stream),
+                                      C.byref(h)))
+        obj.handle = h
+        obj.n = int(n)
+        obj.weighted = False
+        return obj
+
+    def download(self):
+        """The stored event columns, (n_dims, n), FP32 for mixed models."""
+        dt = np.float32 if self.model.precision == "mixed" else np.float64
+        out = np.zeros((self.model.n_dims, self.n), dtype=dt)
+        cols = (C.c_void_p * self.model.n_dims)(*[out[d].ctypes.data for d in range(self.model.n_dims)])
+        check(lib().uml_data_download(self.handle, cols, None))
+        return out
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:
@@ -430,6 +465,17 @@ class Server:
         st = None if start is None else np.ascontiguousarray(start, dtype=np.float64)
         q = uml_request(ev.shape[1], cols, UML_F32 if ev.dtype == np.float32 else UML_F64,
                         None if wt is None else wt.ctypes.data, None if st is None else _dptr(st))
+        t = C.c_uint64()
+        check(lib().uml_server_submit(self.handle, C.byref(q), C.byref(t)))
+        return t.value
+
+    def submit_generated(self, n, seed, gen_theta=None, start=None):
+        """A pseudo-experiment of n events drawn on the device (seed, at
+        gen_theta or the model's values) and fitted from start."""
+        st = None if start is None else np.ascontiguousarray(start, dtype=np.float64)
+        gt = None if gen_theta is None else np.ascontiguousarray(gen_theta, dtype=np.float64)
+        q = uml_request(int(n), None, UML_F64, None, None if st is None else _dptr(st), 1,
+                        C.c_uint64(int(seed)), None if gt is None else _dptr(gt))
         t = C.c_uint64()
         check(lib().uml_server_submit(self.handle, C.byref(q), C.byref(t)))
         return t.value
