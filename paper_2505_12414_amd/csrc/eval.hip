@@ -785,6 +785,21 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   FirstGroup<S, P> first;
   if (full) load_first_group<S, P>(J, base, first);
 
+  // LDS: the pass-1 transpose buffer (also holds the plan while constants
+  // are computed, and the pass-2 sums and plan), and the pass-2 partials
+  constexpr int STRIDE = kBlock + 8;
+  constexpr int PARTS = reduce_parts<K>();
+  constexpr int CH = kBlock / PARTS;
+  // T-sized transpose buffer, reused afterwards for K + UML_MAX_PARAMS
+  // doubles followed by the plan
+  constexpr int PASS2_BYTES =
+      (K + UML_MAX_PARAMS) * sizeof(double) + sizeof(Plan) + sizeof(ConstBlock) + 16;
+  constexpr int LDS_T = (K * STRIDE * sizeof(T) > PASS2_BYTES) ? K * STRIDE
+                                                               : int(PASS2_BYTES / sizeof(T)) + 4;
+  __shared__ __align__(16) T red[LDS_T];
+  __shared__ double red2[K * (PARTS > 16 ? PARTS : 16)];
+  __shared__ int s_flag;
+
   const ConstBlock* __restrict__ gc = J.cst;
   T c[S::ncst];
 #pragma unroll
@@ -796,8 +811,11 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   if (lane < J.npar)
     eq = __double_as_longlong(th[lane]) == __double_as_longlong(gc->theta[lane]);
   const bool hit = __all(eq) && gc->valid;  // the same in every wave
-  if (!hit) {
-    if (tid == 0) compute_constants(*J.plan, th, &s_cb);
+  if (!hit) {  // the plan to LDS first: the constant prologue reads it field by field
+    Plan* s_plan0 = reinterpret_cast<Plan*>(red);
+    bulk_copy16(s_plan0, J.plan, int(sizeof(Plan)));
+    __syncthreads();
+    if (tid == 0) compute_constants(*s_plan0, th, &s_cb);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
@@ -821,19 +839,8 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
       process_tile<S, P, false, false>(J, base, c, xref, acc, first);
   }
 
-  // pass 1: lanes -> tile partial, through LDS in a fixed order
-  constexpr int STRIDE = kBlock + 8;
-  constexpr int PARTS = reduce_parts<K>();
-  constexpr int CH = kBlock / PARTS;
-  // T-sized transpose buffer, reused afterwards for K + UML_MAX_PARAMS
-  // doubles followed by the plan
-  constexpr int PASS2_BYTES =
-      (K + UML_MAX_PARAMS) * sizeof(double) + sizeof(Plan) + sizeof(ConstBlock) + 16;
-  constexpr int LDS_T = (K * STRIDE * sizeof(T) > PASS2_BYTES) ? K * STRIDE
-                                                               : int(PASS2_BYTES / sizeof(T)) + 4;
-  __shared__ __align__(16) T red[LDS_T];
-  __shared__ double red2[K * (PARTS > 16 ? PARTS : 16)];
-  __shared__ int s_flag;
+  // pass 1: lanes -> tile partial, through LDS in a fixed order (buffers
+  // declared above)
 #pragma unroll
   for (int k = 0; k < K; ++k) red[k * STRIDE + tid] = acc[k];
   __syncthreads();

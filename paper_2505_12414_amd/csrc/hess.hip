@@ -67,20 +67,30 @@ static __device__ __noinline__ void hess_constants(const Plan& P, const double* 
   }
 }
 
+// The plan goes to LDS first (the whole wave copies it): the constants are
+// computed by one lane reading it field by field.
+__device__ __forceinline__ void prologue_from_lds(const Plan* __restrict__ plan, const double* theta,
+                                                  ConstBlock* cb, double* hc) {
+  __shared__ __align__(16) Plan sp;
+  const int4* src = reinterpret_cast<const int4*>(plan);
+  int4* dst = reinterpret_cast<int4*>(&sp);
+  for (int k = threadIdx.x; k < int(sizeof(Plan) / 16); k += blockDim.x) dst[k] = src[k];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  compute_constants(sp, theta, cb);
+  hess_constants(sp, theta, hc);
+}
+
 __global__ __launch_bounds__(64) void hess_prologue_kernel(const Plan* __restrict__ plan,
                                                            const double* __restrict__ theta,
                                                            ConstBlock* cb, double* hc) {
-  if (threadIdx.x != 0) return;
-  compute_constants(*plan, theta, cb);
-  hess_constants(*plan, theta, hc);
+  prologue_from_lds(plan, theta, cb, hc);
 }
 
 // The same for a batch: workgroup j prepares job j.
 __global__ __launch_bounds__(64) void hess_prologue_batch_kernel(const HessJob* __restrict__ jobs) {
-  if (threadIdx.x != 0) return;
   const HessJob& J = jobs[blockIdx.x];
-  compute_constants(*J.A.plan, J.theta, const_cast<ConstBlock*>(J.A.cb));
-  hess_constants(*J.A.plan, J.theta, const_cast<double*>(J.A.hc));
+  prologue_from_lds(J.A.plan, J.theta, const_cast<ConstBlock*>(J.A.cb), const_cast<double*>(J.A.hc));
 }
 
 template <class T>
