@@ -89,6 +89,7 @@ struct Gauss {
   static constexpr bool expo = true;
   static constexpr int maxdim = D;
   static constexpr unsigned shift_mask = 1u << D;
+  static constexpr bool pre = false;  // event-only terms stored as columns
   static std::string sig() { return "G" + std::to_string(D); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
@@ -109,6 +110,7 @@ struct Exp {
   static constexpr bool expo = true;
   static constexpr int maxdim = D;
   static constexpr unsigned shift_mask = 1u << D;
+  static constexpr bool pre = false;  // event-only terms stored as columns
   static std::string sig() { return "E" + std::to_string(D); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
@@ -127,6 +129,7 @@ struct Cheb {
   static constexpr bool expo = false;
   static constexpr int maxdim = D;
   static constexpr unsigned shift_mask = 0;
+  static constexpr bool pre = false;  // event-only terms stored as columns
   static std::string sig() { return "C" + std::to_string(D) + "." + std::to_string(N); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
@@ -191,6 +194,7 @@ struct PWave {
   static constexpr bool expo = false;
   static constexpr int maxdim = D0 > D1 ? (D0 > D2 ? D0 : D2) : (D1 > D2 ? D1 : D2);
   static constexpr unsigned shift_mask = 0;
+  static constexpr bool pre = false;  // event-only terms stored as columns
   static std::string sig() {
     return "P" + std::to_string(D0) + std::to_string(D1) + std::to_string(D2);
   }
@@ -219,6 +223,7 @@ struct PWavePre {
   static constexpr bool expo = false;
   static constexpr int maxdim = B + kPWaveTerms - 1;
   static constexpr unsigned shift_mask = 0;
+  static constexpr bool pre = true;  // event-only terms stored as columns
   static std::string sig() { return "Q" + std::to_string(B); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
@@ -240,6 +245,7 @@ struct Comp {
   static constexpr int nmom = 1 + (F::nmom + ... + 0);
   static constexpr int maxdim = std::max({F::maxdim...});
   static constexpr unsigned shift_mask = (F::shift_mask | ... | 0u);
+  static constexpr bool pre = (F::pre || ... || false);
   template <int I>
   using fac = typename TypeAt<I, F...>::type;
   // offsets inside the component's block: constants after log2 K_c,
@@ -266,6 +272,7 @@ struct Shape {
   static constexpr int ncst = (C::ncst + ...);
   static constexpr int ndim = std::max({C::maxdim...}) + 1;
   static constexpr unsigned shift_mask = (C::shift_mask | ...);
+  static constexpr bool pre = (C::pre || ...);
   template <int I>
   using comp = typename TypeAt<I, C...>::type;
   static constexpr int cst_base(int i) {
@@ -597,8 +604,9 @@ __device__ __forceinline__ double to_sgpr(double v) {
 // Wolfe curvature), so mixed-precision rounding cannot stall the search.
 // Stops when EDM = 0.5 g^T V g < edm_tol.  Writes the next trial point and
 // its constants (the next launch's cache) unless the fit is finished.
-__device__ __noinline__ void bfgs_step(const Plan& P, FitState* fs, ConstBlock* cst) {
+__device__ __noinline__ void bfgs_step(const Plan& P, FitState* fs, ConstBlock* cst, ConstBlock* s_cbuf) {
   __shared__ double sv[4][UML_MAX_PARAMS];  // s, y, V y, new gradient
+  __shared__ double s_th[UML_MAX_PARAMS];    // the next trial point
   __shared__ double sc[4];
   __shared__ int act, fin;
   const int tid = threadIdx.x, nf = P.nfree;
@@ -740,7 +748,11 @@ __device__ __noinline__ void bfgs_step(const Plan& P, FitState* fs, ConstBlock* 
   }
   if (tid < nf) fs->theta[P.free_idx[tid]] = fs->x[tid] + fs->alpha * fs->p[tid];
   __syncthreads();
-  if (tid == 0) compute_constants(P, fs->theta, cst);  // the next launch's cache
+  if (tid < P.npar) s_th[tid] = fs->theta[tid];
+  __syncthreads();
+  compute_constants(lds(&P), lds(s_th), lds(s_cbuf));  // the next launch's cache, built in LDS
+  __syncthreads();
+  store_const_block(cst, *s_cbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -754,8 +766,31 @@ __host__ __device__ constexpr int reduce_parts() {
   return p;
 }
 
+// A point that misses the cache: the plan and theta go to LDS (buf, at least
+// sizeof(Plan) + UML_MAX_PARAMS doubles; both reads in flight together), then
+// the workgroup runs the prologue into cb.  Ends with a workgroup barrier.
+__device__ __forceinline__ void miss_prologue(const Plan* __restrict__ plan, const double* __restrict__ th,
+                                           int npar, void* buf, ConstBlock* cb) {
+  Plan* s_plan = static_cast<Plan*>(buf);
+  double* s_th = reinterpret_cast<double*>(static_cast<char*>(buf) + sizeof(Plan));
+  bulk_copy16(s_plan, plan, int(sizeof(Plan)));
+  if (int(threadIdx.x) < npar) s_th[threadIdx.x] = th[threadIdx.x];
+  __syncthreads();
+  compute_constants(lds(s_plan), lds(s_th), lds(cb));
+  __syncthreads();
+}
+
+// Waves per SIMD the kernel is built for.  The mixed-precision kernels keep
+// four (at most 128 VGPRs): their FP32 event loops need that latency hiding,
+// and the largest of them sits right at the limit.  The FP64 kernels and those
+// reading precomputed terms hold more per event and are left unconstrained.
 template <class S, class P>
-__global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* __restrict__ jobs,
+__host__ __device__ constexpr int eval_min_waves() {
+  return (P::VW == 4 && !S::pre) ? 4 : 1;
+}
+
+template <class S, class P>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min_waves<S, P>()))) void eval_kernel(const Job j0, const Job* __restrict__ jobs,
                                                       const int2* __restrict__ tmap,
                                                       const double* __restrict__ theta_override,
                                                       double* __restrict__ out_override) {
@@ -811,12 +846,8 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const Job j0, const Job* _
   if (lane < J.npar)
     eq = __double_as_longlong(th[lane]) == __double_as_longlong(gc->theta[lane]);
   const bool hit = __all(eq) && gc->valid;  // the same in every wave
-  if (!hit) {  // the plan to LDS first: the constant prologue reads it field by field
-    Plan* s_plan0 = reinterpret_cast<Plan*>(red);
-    bulk_copy16(s_plan0, J.plan, int(sizeof(Plan)));
-    __syncthreads();
-    if (tid == 0) compute_constants(*s_plan0, th, &s_cb);
-    __syncthreads();
+  if (!hit) {
+    miss_prologue(J.plan, th, J.npar, red, &s_cb);
 #pragma unroll
     for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
 #pragma unroll
@@ -918,7 +949,7 @@ top_level:
   epilogue(*s_plan, hit ? s_gc : &s_cb, tot, (out_override && !tmap) ? out_override : J.out);
   if (J.fit) {
     __syncthreads();
-    bfgs_step(*s_plan, J.fit, J.cst);
+    bfgs_step(*s_plan, J.fit, J.cst, s_gc);  // s_gc is free once the epilogue is done
   }
 }
 

@@ -28,67 +28,71 @@
 
 namespace uml {
 
-// Second derivatives that the gradient does not need: d2 ln D of the
-// Gaussian normalisation D = Phi(zb) - Phi(za) in (mu, sigma), and -Var[x]
-// of the truncated exponential (d2 ln p / d lambda^2).
-static __device__ __noinline__ void hess_constants(const Plan& P, const double* __restrict__ th,
-                                                   double* hc) {
+// Second derivatives that the gradient does not need, for one factor: d2 ln D
+// of the Gaussian normalisation D = Phi(zb) - Phi(za) in (mu, sigma), and
+// -Var[x] of the truncated exponential (d2 ln p / d lambda^2).
+static __device__ __forceinline__ void hess_factor_constants(const FactorPlan& F, const double* __restrict__ th,
+                                                             double* h) {
   const double kInvSqrt2Pi = 0.39894228040143267794;
-  for (int f = 0; f < P.nfac; ++f) {
-    const FactorPlan& F = P.fac[f];
-    double* h = hc + 4 * f;
-    h[0] = h[1] = h[2] = h[3] = 0.0;
-    const double a = F.lo[0], b = F.hi[0];
-    if (F.kind == FK_GAUSS) {
-      const double mu = th[F.par[0]], sg = th[F.par[1]];
-      const double za = (a - mu) / sg, zb = (b - mu) / sg;
-      const double D = d_phi_diff(za, zb);
-      const double pa = nl_exp(-0.5 * za * za) * kInvSqrt2Pi, pb = nl_exp(-0.5 * zb * zb) * kInvSqrt2Pi;
-      const double s2 = sg * sg;
-      const double Dm = (pa - pb) / sg, Ds = (za * pa - zb * pb) / sg;
-      const double Dmm = (za * pa - zb * pb) / s2;
-      const double Dms = (-(pa - pb) + za * za * pa - zb * zb * pb) / s2;
-      const double Dss = (-2.0 * za * pa + za * za * za * pa + 2.0 * zb * pb - zb * zb * zb * pb) / s2;
-      h[0] = Dmm / D - Dm * Dm / (D * D);
-      h[1] = Dms / D - Dm * Ds / (D * D);
-      h[2] = Dss / D - Ds * Ds / (D * D);
-    } else if (F.kind == FK_EXP) {
-      const double lam = th[F.par[0]], L = b - a, z = lam * L;
-      double hp;  // h'(z), h(z) = 1/(1 - e^{-z}) - 1/z; Var[x] = L^2 h'(lambda L)
-      if (fabs(z) < 0.05) {
-        const double z2 = z * z;
-        hp = 1.0 / 12.0 + z2 * (-1.0 / 240.0 + z2 * (1.0 / 6048.0 - z2 / 172800.0));
-      } else {
-        const double em = nl_expm1(-z);
-        hp = 1.0 / (z * z) - nl_exp(-z) / (em * em);
-      }
-      h[0] = -L * L * hp;
+  h[0] = h[1] = h[2] = h[3] = 0.0;
+  const double a = F.lo[0], b = F.hi[0];
+  if (F.kind == FK_GAUSS) {
+    const double mu = th[F.par[0]], sg = th[F.par[1]];
+    const double za = (a - mu) / sg, zb = (b - mu) / sg;
+    const double D = d_phi_diff(za, zb);
+    const double pa = p_exp(-0.5 * za * za) * kInvSqrt2Pi, pb = p_exp(-0.5 * zb * zb) * kInvSqrt2Pi;
+    const double s2 = sg * sg;
+    const double Dm = (pa - pb) / sg, Ds = (za * pa - zb * pb) / sg;
+    const double Dmm = (za * pa - zb * pb) / s2;
+    const double Dms = (-(pa - pb) + za * za * pa - zb * zb * pb) / s2;
+    const double Dss = (-2.0 * za * pa + za * za * za * pa + 2.0 * zb * pb - zb * zb * zb * pb) / s2;
+    h[0] = Dmm / D - Dm * Dm / (D * D);
+    h[1] = Dms / D - Dm * Ds / (D * D);
+    h[2] = Dss / D - Ds * Ds / (D * D);
+  } else if (F.kind == FK_EXP) {
+    const double lam = th[F.par[0]], L = b - a, z = lam * L;
+    double hp;  // h'(z), h(z) = 1/(1 - e^{-z}) - 1/z; Var[x] = L^2 h'(lambda L)
+    if (fabs(z) < 0.05) {
+      const double z2 = z * z;
+      hp = 1.0 / 12.0 + z2 * (-1.0 / 240.0 + z2 * (1.0 / 6048.0 - z2 / 172800.0));
+    } else {
+      const double em = p_expm1(-z);
+      hp = 1.0 / (z * z) - p_exp(-z) / (em * em);
     }
+    h[0] = -L * L * hp;
   }
 }
 
-// The plan goes to LDS first (the whole wave copies it): the constants are
-// computed by one lane reading it field by field.
+// Both prologues of a Hessian pass, by the whole workgroup (256 threads): the
+// plan and theta go to LDS first, then compute_constants, then lane f of the
+// wave of its kind computes factor f's second-derivative constants.
 __device__ __forceinline__ void prologue_from_lds(const Plan* __restrict__ plan, const double* theta,
                                                   ConstBlock* cb, double* hc) {
   __shared__ __align__(16) Plan sp;
+  __shared__ __align__(16) ConstBlock scb;
+  __shared__ double sth[UML_MAX_PARAMS];
   const int4* src = reinterpret_cast<const int4*>(plan);
   int4* dst = reinterpret_cast<int4*>(&sp);
   for (int k = threadIdx.x; k < int(sizeof(Plan) / 16); k += blockDim.x) dst[k] = src[k];
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  compute_constants(sp, theta, cb);
-  hess_constants(sp, theta, hc);
+  for (int k = threadIdx.x; k < sp.npar; k += blockDim.x) sth[k] = theta[k];
+  __syncthreads();
+  compute_constants(lds(&sp), lds(sth), lds(&scb));
+  const int lane = threadIdx.x & 63;
+  if (lane < sp.nfac && prologue_wave(sp.fac[lane].kind, blockDim.x >> 6) == int(threadIdx.x >> 6))
+    hess_factor_constants(sp.fac[lane], sth, hc + 4 * lane);
+  __syncthreads();
+  store_const_block(cb, scb);
 }
 
-__global__ __launch_bounds__(64) void hess_prologue_kernel(const Plan* __restrict__ plan,
+__global__ __launch_bounds__(256) void hess_prologue_kernel(const Plan* __restrict__ plan,
                                                            const double* __restrict__ theta,
                                                            ConstBlock* cb, double* hc) {
   prologue_from_lds(plan, theta, cb, hc);
 }
 
 // The same for a batch: workgroup j prepares job j.
-__global__ __launch_bounds__(64) void hess_prologue_batch_kernel(const HessJob* __restrict__ jobs) {
+__global__ __launch_bounds__(256) void hess_prologue_batch_kernel(const HessJob* __restrict__ jobs) {
   const HessJob& J = jobs[blockIdx.x];
   prologue_from_lds(J.A.plan, J.theta, const_cast<ConstBlock*>(J.A.cb), const_cast<double*>(J.A.hc));
 }
@@ -353,7 +357,7 @@ size_t hess_lds_bytes(int row_len, int chunk, int precision) {
 
 void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, double* d_hc,
                     double* d_out, int precision, hipStream_t s) {
-  hipLaunchKernelGGL(hess_prologue_kernel, dim3(1), dim3(64), 0, s, A.plan, d_theta, d_cb, d_hc);
+  hipLaunchKernelGGL(hess_prologue_kernel, dim3(1), dim3(256), 0, s, A.plan, d_theta, d_cb, d_hc);
   const size_t lds = hess_lds_bytes(A.row_len, A.chunk, precision);
   if (precision == UML_MIXED)
     hipLaunchKernelGGL(hess_kernel<float>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
@@ -366,7 +370,7 @@ void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, 
 void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, int n_map, int row_len,
                           int chunk, int n_sums, int precision, hipStream_t s) {
   if (n_jobs <= 0) return;
-  hipLaunchKernelGGL(hess_prologue_batch_kernel, dim3(n_jobs), dim3(64), 0, s, d_jobs);
+  hipLaunchKernelGGL(hess_prologue_batch_kernel, dim3(n_jobs), dim3(256), 0, s, d_jobs);
   const size_t lds = hess_lds_bytes(row_len, chunk, precision);
   if (precision == UML_MIXED)
     hipLaunchKernelGGL(hess_batch_kernel<float>, dim3(n_map), dim3(kBlock), lds, s, d_jobs, d_map);

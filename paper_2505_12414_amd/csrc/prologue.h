@@ -1,6 +1,9 @@
 // The prologue: FP64 parameter-only terms of one parameter point, shared by
-// the event kernels and the Hessian kernel.  Everything here runs once per
-// point on one lane.
+// the event kernels and the Hessian kernel.  A workgroup runs it in three
+// stages: each factor and each mixture fraction is the task of one lane, and
+// the slow pieces (the erfc, exp and expm1 of the Gaussian and exponential
+// normalisations, then the per-kind constants) run in different waves, so its
+// latency is that of the slowest piece rather than the sum over all factors.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,55 +14,111 @@
 
 namespace uml {
 
-// The FP64 library functions are called, not inlined, from the once-per-point
-// code below: the event kernels' register budget is the maximum over every
-// function they can reach, and the event loop must not pay for erfc.
-static __device__ __noinline__ double nl_erfc(double x) { return erfc(x); }
-static __device__ __noinline__ double nl_exp(double x) { return exp(x); }
-static __device__ __noinline__ double nl_log(double x) { return log(x); }
-static __device__ __noinline__ double nl_log2(double x) { return log2(x); }
-static __device__ __noinline__ double nl_expm1(double x) { return expm1(x); }
+// Everything here is inlined into its callers (no call ABI): the prologue's
+// FP64 work runs before the event loop, so the register allocator can give
+// the loop its full budget, and each out-of-line call would save and restore
+// registers through scratch memory (measured to dominate the latency of a
+// one-lane prologue built from such calls).
+static __device__ __forceinline__ double p_erfc(double x) { return erfc(x); }
+static __device__ __forceinline__ double p_exp(double x) { return exp(x); }
+static __device__ __forceinline__ double p_log(double x) { return log(x); }
+static __device__ __forceinline__ double p_log2(double x) { return log2(x); }
+static __device__ __forceinline__ double p_expm1(double x) { return expm1(x); }
 
-// Phi(zb) - Phi(za), za < zb, with erfc where both share a sign.
-static __device__ __noinline__ double d_phi_diff(double za, double zb) {
+// Phi(zb) - Phi(za), za < zb, from two erfc values, taken where both
+// arguments share a sign: phi_diff_args gives the arguments (u, v),
+// phi_diff_from combines erfc(u) and erfc(v).
+static __device__ __forceinline__ void phi_diff_args(double za, double zb, double& u, double& v) {
   const double r = 0.70710678118654752440;
-  if (za >= 0.0) return 0.5 * (nl_erfc(za * r) - nl_erfc(zb * r));
-  if (zb <= 0.0) return 0.5 * (nl_erfc(-zb * r) - nl_erfc(-za * r));
-  return 1.0 - 0.5 * nl_erfc(zb * r) - 0.5 * nl_erfc(-za * r);
-}
-
-// Mean offset of a truncated exponential: E[x] - a = L * h(lambda L),
-// h(z) = 1/(1 - e^{-z}) - 1/z, by its Taylor series near z = 0.
-static __device__ __noinline__ double d_exp_h(double z) {
-  if (fabs(z) < 0.05) {
-    const double z2 = z * z;
-    return 0.5 + z * (1.0 / 12.0 + z2 * (-1.0 / 720.0 + z2 * (1.0 / 30240.0 - z2 / 1209600.0)));
+  if (za >= 0.0) {
+    u = za * r;
+    v = zb * r;
+  } else if (zb <= 0.0) {
+    u = -zb * r;
+    v = -za * r;
+  } else {
+    u = zb * r;
+    v = -za * r;
   }
-  return -1.0 / nl_expm1(-z) - 1.0 / z;
+}
+static __device__ __forceinline__ double phi_diff_from(double za, double zb, double eu, double ev) {
+  if (za >= 0.0 || zb <= 0.0) return 0.5 * (eu - ev);
+  return 1.0 - 0.5 * eu - 0.5 * ev;
+}
+static __device__ __forceinline__ double d_phi_diff(double za, double zb) {
+  double u, v;
+  phi_diff_args(za, zb, u, v);
+  return phi_diff_from(za, zb, p_erfc(u), p_erfc(v));
 }
 
 static constexpr double kLog2e = 1.4426950408889634074;
 static constexpr double kSqrt2Pi = 2.5066282746310005024;
 
+// Stage 1 of the prologue: the transcendental functions of the Gaussian and
+// exponential factors, in two halves that run on different waves.  tr:
+//   Gaussian     half 0: tr[0] = erfc(u), tr[2] = exp(-za^2/2)
+//                half 1: tr[1] = erfc(v), tr[3] = exp(-zb^2/2)
+//   exponential  half 0: tr[0] = expm1(lambda L)
+//                half 1: tr[1] = expm1(-lambda L) (unused near lambda L = 0)
+static __device__ __forceinline__ void factor_stage1(const FactorPlan& F, const double* __restrict__ th,
+                                                     int half, double* tr) {
+  if (F.kind == FK_GAUSS) {
+    const double mu = th[F.par[0]], sg = th[F.par[1]];
+    const double za = (F.lo[0] - mu) / sg, zb = (F.hi[0] - mu) / sg;
+    double u, v;
+    phi_diff_args(za, zb, u, v);
+    if (half == 0) {
+      tr[0] = p_erfc(u);
+      tr[2] = p_exp(-0.5 * za * za);
+    } else {
+      tr[1] = p_erfc(v);
+      tr[3] = p_exp(-0.5 * zb * zb);
+    }
+  } else if (F.kind == FK_EXP) {
+    const double lam = th[F.par[0]], z = lam * (F.hi[0] - F.lo[0]);
+    if (half == 0)
+      tr[0] = lam == 0.0 ? 0.0 : p_expm1(z);
+    else
+      tr[1] = (lam == 0.0 || fabs(z) < 0.05) ? 0.0 : p_expm1(-z);
+  }
+}
+
+static constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+
+// Output of one factor's kernel constants, written in both precisions from
+// registers (the FP32 copies are what the mixed-precision kernels load).
+struct KOut {
+  double* d;
+  float* f;
+  __device__ __forceinline__ void put(int i, double v) const {
+    d[i] = v;
+    f[i] = float(v);
+  }
+};
+
 // Gaussian normalised on [a, b] (Eq. 2): constants of the kernel, the
 // epilogue coefficients of its gradient terms, and log2 of its prefactor
-// 1 / (sigma sqrt(2 pi) (Phi(zb) - Phi(za))).
+// 1 / (sigma sqrt(2 pi) (Phi(zb) - Phi(za))); tr from stage 1.
 //   d ln g / d mu    = d / sigma^2 - (phi(za) - phi(zb)) / (sigma D)
 //   d ln g / d sigma = d^2 / sigma^3 - 1/sigma - (za phi(za) - zb phi(zb)) / (sigma D)
-static __device__ __noinline__ bool gauss_constants(const FactorPlan& F, const double* __restrict__ th,
-                                             double* kc, double* ec, double* lnorm2) {
+// (1/sigma and 1/D are formed once: the divisions are long dependent chains.)
+static __device__ __forceinline__ bool gauss_constants(const FactorPlan& F, const double* __restrict__ th,
+                                                       const double* tr, const KOut& k, double* ec,
+                                                       double* lnorm2) {
   const double a = F.lo[0], b = F.hi[0];
   const double mu = th[F.par[0]], sg = th[F.par[1]];
-  const double za = (a - mu) / sg, zb = (b - mu) / sg;
-  const double D = d_phi_diff(za, zb);
-  const double pa = nl_exp(-0.5 * za * za) / kSqrt2Pi, pb = nl_exp(-0.5 * zb * zb) / kSqrt2Pi;
-  kc[0] = mu - F.xref;
-  kc[1] = kLog2e / (2.0 * sg * sg);
-  *lnorm2 = -nl_log2(sg * kSqrt2Pi * D);
-  ec[0] = 1.0 / (sg * sg);                           // x sum r d
-  ec[1] = -(pa - pb) / (sg * D);                     // x sum r
-  ec[2] = 1.0 / (sg * sg * sg);                      // x sum r d^2
-  ec[3] = -(1.0 / sg + (za * pa - zb * pb) / (sg * D));  // x sum r
+  const double za = (a - mu) / sg, zb = (b - mu) / sg;  // as in stage 1
+  const double isg = 1.0 / sg;
+  const double D = phi_diff_from(za, zb, tr[0], tr[1]);
+  const double iD = 1.0 / D;
+  const double pa = tr[2] * kInvSqrt2Pi, pb = tr[3] * kInvSqrt2Pi;
+  k.put(0, mu - F.xref);
+  k.put(1, 0.5 * kLog2e * (isg * isg));
+  *lnorm2 = -p_log2(sg * kSqrt2Pi * D);
+  ec[0] = isg * isg;                                 // x sum r d
+  ec[1] = -(pa - pb) * (isg * iD);                   // x sum r
+  ec[2] = isg * isg * isg;                           // x sum r d^2
+  ec[3] = -(isg + (za * pa - zb * pb) * (isg * iD)); // x sum r
   return sg > 0.0;
 }
 
@@ -67,19 +126,29 @@ static __device__ __noinline__ bool gauss_constants(const FactorPlan& F, const d
 // 2^{lambda log2(e) x'} with x' = x - xref; the prefactor e^{lambda xref}/N
 // is written through expm1 so that small |lambda| keeps full precision.
 //   d ln p / d lambda = x' - (E[x] - xref)
-static __device__ __noinline__ bool exp_constants(const FactorPlan& F, const double* __restrict__ th,
-                                           double* kc, double* ec, double* lnorm2) {
+// with E[x] - a = L h(lambda L), h(z) = 1/(1 - e^{-z}) - 1/z, by its Taylor
+// series near z = 0; tr from stage 1.
+static __device__ __forceinline__ bool exp_constants(const FactorPlan& F, const double* __restrict__ th,
+                                                     const double* tr, const KOut& k, double* ec,
+                                                     double* lnorm2) {
   const double a = F.lo[0], b = F.hi[0], xr = F.xref, L = b - a;
   const double lam = th[F.par[0]];
-  kc[0] = lam * kLog2e;
+  k.put(0, lam * kLog2e);
   ec[0] = 1.0;
   if (lam == 0.0) {
-    *lnorm2 = -nl_log2(L);
+    *lnorm2 = -p_log2(L);
     ec[1] = -(a + 0.5 * L - xr);
   } else {
     const double z = lam * L;
-    *lnorm2 = (lam * (xr - a) - nl_log(nl_expm1(z) / lam)) * kLog2e;
-    ec[1] = -(a - xr + L * d_exp_h(z));
+    *lnorm2 = (lam * (xr - a) - p_log(tr[0] / lam)) * kLog2e;
+    double h;
+    if (fabs(z) < 0.05) {
+      const double z2 = z * z;
+      h = 0.5 + z * (1.0 / 12.0 + z2 * (-1.0 / 720.0 + z2 * (1.0 / 30240.0 - z2 / 1209600.0)));
+    } else {
+      h = -1.0 / tr[1] - 1.0 / z;
+    }
+    ec[1] = -(a - xr + L * h);
   }
   return true;
 }
@@ -87,77 +156,177 @@ static __device__ __noinline__ bool exp_constants(const FactorPlan& F, const dou
 // Chebyshev series 1 + sum_j c_j T_j(u) on [a, b], u = (2x - a - b)/(b - a),
 // with norm N_C = (b - a) + sum_{j even} c_j (b - a)/(1 - j^2).
 //   d ln p / d c_j = T_j / (1 + sum c T) - J_j / N_C,  J_j = d N_C / d c_j
-static __device__ __noinline__ bool cheb_constants(const FactorPlan& F, const double* __restrict__ th,
-                                            double* kc, double* ec) {
-  const double a = F.lo[0], b = F.hi[0], xr = F.xref;
-  const int k = F.order;
-  double N = b - a;
-  for (int jj = 1; jj <= k; ++jj) {
-    const double J = (jj % 2 == 0) ? (b - a) / (1.0 - double(jj * jj)) : 0.0;
-    N += th[F.par[jj - 1]] * J;
-    ec[k + jj - 1] = J;
+// Unrolled to the maximum order, so the coefficient reads go out together.
+static __device__ __forceinline__ bool cheb_constants(const FactorPlan& F, const double* __restrict__ th,
+                                                      const KOut& k, double* ec) {
+  const double a = F.lo[0], b = F.hi[0], xr = F.xref, L = b - a;
+  const int n = F.order;
+  double J[kMaxCheb], c[kMaxCheb];
+#pragma unroll
+  for (int j = 0; j < kMaxCheb; ++j) {
+    const int jj = j + 1;
+    J[j] = (jj % 2 == 0) ? L / (1.0 - double(jj * jj)) : 0.0;
+    c[j] = th[F.par[j < n ? j : 0]];
   }
-  kc[0] = 2.0 / (b - a);
-  kc[1] = (2.0 * xr - a - b) / (b - a);
-  kc[2] = 1.0 / N;
-  for (int jj = 1; jj <= k; ++jj) {
-    kc[2 + jj] = th[F.par[jj - 1]] / N;
-    ec[jj - 1] = 1.0 / N;                      // x sum q T_j
-    ec[k + jj - 1] = -ec[k + jj - 1] / N;      // x sum r
-  }
+  double N = L;
+#pragma unroll
+  for (int j = 0; j < kMaxCheb; ++j)
+    if (j < n) N += c[j] * J[j];
+  const double iL = 1.0 / L, iN = 1.0 / N;
+  k.put(0, 2.0 * iL);
+  k.put(1, (2.0 * xr - a - b) * iL);
+  k.put(2, iN);
+#pragma unroll
+  for (int j = 0; j < kMaxCheb; ++j)
+    if (j < n) {
+      k.put(3 + j, c[j] * iN);
+      ec[j] = iN;              // x sum q T_j
+      ec[n + j] = -J[j] * iN;  // x sum r
+    }
   return true;
 }
 
 // P-wave density (Eq. 4): coefficients 9/(32 pi) {1, FL, S3, 4 S4, 2 S5,
 // 4/3 AFB, 2 S7, 4 S8, 2 S9}; d ln A / d S_k = 9/(32 pi) s_k b_k / A.
-static __device__ __noinline__ void pwave_constants(const FactorPlan& F, const double* __restrict__ th,
-                                             double* kc, double* ec) {
+static __device__ __forceinline__ void pwave_constants(const FactorPlan& F, const double* __restrict__ th,
+                                                       const KOut& k, double* ec) {
   const double kap = 9.0 / (32.0 * M_PI);
   const double scale[8] = {1.0, 1.0, 4.0, 2.0, 4.0 / 3.0, 2.0, 4.0, 2.0};
-  kc[0] = kap;
-  for (int k = 0; k < 8; ++k) {
-    kc[1 + k] = kap * scale[k] * th[F.par[k]];
-    ec[k] = kap * scale[k];
+  k.put(0, kap);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    k.put(1 + i, kap * scale[i] * th[F.par[i]]);
+    ec[i] = kap * scale[i];
   }
 }
 
-// The prologue: every parameter-only term of the point theta (Sec. 2.4.1).
-static __device__ __noinline__ void compute_constants(const Plan& P, const double* __restrict__ th,
-                                               ConstBlock* cb) {
+// Stage 2 for one factor: kernel constants, epilogue constants ec and log2
+// of its parameter-only prefactor; false outside the factor's domain.
+static __device__ __forceinline__ bool factor_constants(const FactorPlan& F, const double* __restrict__ th,
+                                                        const double* tr, const KOut& k, double* ec,
+                                                        double* lnorm2) {
+  *lnorm2 = 0.0;
+  switch (F.kind) {
+    case FK_GAUSS: return gauss_constants(F, th, tr, k, ec, lnorm2);
+    case FK_EXP: return exp_constants(F, th, tr, k, ec, lnorm2);
+    case FK_CHEB: return cheb_constants(F, th, k, ec);
+    case FK_PWAVE: pwave_constants(F, th, k, ec); return true;
+  }
+  return false;
+}
+
+static_assert(kMaxFac <= 32 && kMaxComp * 8 <= 32, "prologue tasks: factors on lanes 0-31, fractions on 32-63");
+
+// The waves of the two stages, chosen so that the slow pieces run side by
+// side on different SIMDs: stage 1 puts the Gaussian halves on waves 0 and 1
+// and the exponential halves (and the fractions) on waves 2 and 3; stage 2
+// gives each factor kind a wave of its own.
+static __device__ __forceinline__ int stage1_wave(int kind, int half, int nwaves) {
+  return ((kind == FK_GAUSS ? 0 : 2) + half) % nwaves;
+}
+static __device__ __forceinline__ int prologue_wave(int kind, int nwaves) {
+  return (kind >= FK_GAUSS && kind <= FK_PWAVE) ? (kind - FK_GAUSS) % nwaves : 0;
+}
+
+// LDS-qualified views: the prologue's inputs and output are typed as LDS, so
+// every access is a direct LDS one.  (A generic, flat, access is tracked by
+// both the vector-memory and the LDS counters: each later LDS read would wait
+// for it.)
+using LdsPlan = const __attribute__((address_space(3))) Plan;
+using LdsDouble = const __attribute__((address_space(3))) double;
+using LdsConstBlock = __attribute__((address_space(3))) ConstBlock;
+template <class T>
+static __device__ __forceinline__ auto lds(T* p) {
+  return (__attribute__((address_space(3))) T*)p;
+}
+
+// The prologue: every parameter-only term of the point th (Sec. 2.4.1 and
+// Eq. 3) written to cb.  Called by every thread of a workgroup whose size is
+// a multiple of 64, at most 1024 (it synchronises the workgroup; the caller
+// synchronises again before other threads read cb).  P, th (all npar
+// parameters) and cb sit in LDS (store_const_block copies cb out).
+//   stage 1  lane f of the waves of stage1_wave: the transcendental halves of
+//            factor f; lane 32 + 8c + k of wave 2: fraction entry k of
+//            component c (log2 and d ln F_c / d f);
+//   stage 2  lane f of the wave of its kind: factor f's constants;
+//   stage 3  lane c of wave 0: component c's log2 prefactor, summed in a
+//            fixed order (its fractions, then its factors), so the result
+//            does not depend on timing.
+static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDouble* __restrict__ th_lds,
+                                                         LdsConstBlock* cb_lds) {
+  __shared__ double s_tr[kMaxFac][4];      // stage-1 results per factor
+  __shared__ double s_ln2[kMaxFac];        // log2 prefactor of each factor
+  __shared__ double s_fl2[kMaxComp * 8];   // log2 of each fraction entry
+  __shared__ int s_bad[16];                // per wave: a task left the domain
+  const Plan& P = *(const Plan*)P_lds;
+  const double* __restrict__ th = (const double*)th_lds;
+  ConstBlock* cb = (ConstBlock*)cb_lds;
+  const int tid = threadIdx.x;
+  const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
   bool ok = true;
-  for (int i = 0; i < P.npar; ++i) cb->theta[i] = th[i];
-  for (int ci = 0; ci < P.ncomp; ++ci) {
-    const CompPlan& C = P.comp[ci];
-    double lk2 = 0.0;
-    for (int k = 0; k < C.nfrac; ++k) {
+  // stage 1
+  if (lane < P.nfac) {
+    const FactorPlan& F = P.fac[lane];
+    if (F.kind == FK_GAUSS || F.kind == FK_EXP)
+      for (int h = 0; h < 2; ++h)
+        if (stage1_wave(F.kind, h, nw) == w) factor_stage1(F, th, h, s_tr[lane]);
+  }
+  if (lane >= 32 && w == 2 % nw) {
+    const int c = (lane - 32) >> 3, k = (lane - 32) & 7;
+    if (c < P.ncomp && k < P.comp[c].nfrac) {
+      const CompPlan& C = P.comp[c];
       const double f = th[C.frac_par[k]];
-      if (!(f >= 0.0 && f <= 1.0)) ok = false;
-      lk2 += nl_log2(C.frac_sign[k] > 0 ? f : 1.0 - f);
+      ok = f >= 0.0 && f <= 1.0;
+      s_fl2[lane - 32] = p_log2(C.frac_sign[k] > 0 ? f : 1.0 - f);
       cb->e[C.frac_ec[k]] = C.frac_sign[k] > 0 ? 1.0 / f : -1.0 / (1.0 - f);  // d ln F_c / d f
     }
-    for (int j = 0; j < C.nfac; ++j) {
-      const FactorPlan& F = P.fac[C.fac[j]];
-      double* kc = cb->d + F.cst;
-      double* ec = cb->e + F.ecst;
-      double ln2 = 0.0;
-      switch (F.kind) {
-        case FK_GAUSS: ok = gauss_constants(F, th, kc, ec, &ln2) && ok; break;
-        case FK_EXP: ok = exp_constants(F, th, kc, ec, &ln2) && ok; break;
-        case FK_CHEB: ok = cheb_constants(F, th, kc, ec) && ok; break;
-        case FK_PWAVE: pwave_constants(F, th, kc, ec); break;
-        default: ok = false;
-      }
-      lk2 += ln2;
+  }
+  if (tid < P.ndim) {
+    cb->xd[tid] = P.xref[tid];
+    cb->xf[tid] = float(P.xref[tid]);
+  }
+  __syncthreads();
+  // stage 2
+  if (lane < P.nfac && prologue_wave(P.fac[lane].kind, nw) == w) {
+    const FactorPlan& F = P.fac[lane];
+    const KOut ko{cb->d + F.cst, cb->f + F.cst};
+    ok = factor_constants(F, th, s_tr[lane], ko, cb->e + F.ecst, &s_ln2[lane]) && ok;
+  }
+  if (w == nw - 1 && lane >= 32 && lane - 32 < P.npar) cb->theta[lane - 32] = th[lane - 32];
+  const bool wave_bad = __ballot(ok ? 0 : 1) != 0;
+  if (lane == 0 && w < 16) s_bad[w] = wave_bad ? 1 : 0;
+  __syncthreads();
+  // stage 3 (unrolled to the maximum counts, so the reads go out together)
+  if (tid < P.ncomp) {
+    const CompPlan& C = P.comp[tid];
+    double lk2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double v = s_fl2[tid * 8 + k];
+      if (k < C.nfrac) lk2 += v;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxFacPerComp; ++j) {
+      const int f = j < C.nfac ? C.fac[j] : 0;
+      const double v = s_ln2[f];
+      if (j < C.nfac) lk2 += v;
     }
     cb->d[C.cst_lk2] = lk2;
+    cb->f[C.cst_lk2] = float(lk2);
   }
-  for (int i = 0; i < P.ncst; ++i) cb->f[i] = float(cb->d[i]);
-  for (int d = 0; d < P.ndim; ++d) {
-    cb->xd[d] = P.xref[d];
-    cb->xf[d] = float(P.xref[d]);
+  if (tid == 0) {
+    int bad = 0;
+    for (int i = 0; i < nw && i < 16; ++i) bad |= s_bad[i];
+    cb->domain_ok = bad ? 0 : 1;
+    cb->valid = 1;
   }
-  cb->domain_ok = ok ? 1 : 0;
-  cb->valid = 1;
+}
+
+// Copies a constant block from LDS to global memory, by the whole workgroup.
+static __device__ __forceinline__ void store_const_block(ConstBlock* dst, const ConstBlock& src) {
+  const int4* s4 = reinterpret_cast<const int4*>(&src);
+  int4* d4 = reinterpret_cast<int4*>(dst);
+  for (int i = threadIdx.x; i < int(sizeof(ConstBlock) / 16); i += blockDim.x) d4[i] = s4[i];
 }
 
 }  // namespace uml
