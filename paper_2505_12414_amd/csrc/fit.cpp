@@ -50,11 +50,10 @@ int hess_sums(const uml_model* m) { return 1 + m->plan.nfree + 2 * m->hplan.npai
 static int hess_chunk(const uml_model* m) {
   const Plan& P = m->plan;
   const int row = hess_row_len(P, m->hplan);
-  const size_t fixed = hess_lds_bytes(row, 0, P.precision);
-  const size_t esz = P.precision == UML_MIXED ? 4 : 8;
+  const int mat = hess_mat_bytes(P, m->hplan);
   int chunk = kBlock;
-  while (chunk > 1 && fixed + size_t(row) * chunk * esz > 60 * 1024) chunk /= 2;
-  return fixed + size_t(row) * chunk * esz > 64 * 1024 ? 0 : chunk;
+  while (chunk > 1 && hess_lds_bytes(row, chunk, P.precision, mat) > 60 * 1024) chunk /= 2;
+  return hess_lds_bytes(row, chunk, P.precision, mat) > 64 * 1024 ? 0 : chunk;
 }
 
 // Arguments of the Hessian pass of dataset d at the device parameter vector
@@ -89,6 +88,7 @@ static int hess_job(const uml_model* m, const uml_data* d, const double* d_theta
   A.chunk = chunk;
   A.row_len = hess_row_len(P, m->hplan);
   A.n_sums = HL.M;
+  A.mat_bytes = hess_mat_bytes(P, m->hplan);
   J.theta = d_theta;
   J.out = d_out ? d_out : reinterpret_cast<double*>(base + HL.o_out);
   return UML_OK;
@@ -131,8 +131,8 @@ int hessian_queue_batch(const uml_model* m, uml_data* const* ds, const double* c
   }
   UML_HIP_CHECK(hipMemcpyAsync(d_jobs, h_jobs, sizeof(HessJob) * n, hipMemcpyHostToDevice, s));
   UML_HIP_CHECK(hipMemcpyAsync(d_map, h_map, sizeof(int2) * n_map, hipMemcpyHostToDevice, s));
-  launch_hessian_batch(d_jobs, n, d_map, n_map, h_jobs[0].A.row_len, h_jobs[0].A.chunk, M,
-                       m->plan.precision, s);
+  launch_hessian_batch(d_jobs, n, d_map, n_map, h_jobs[0].A.row_len, h_jobs[0].A.chunk, h_jobs[0].A.mat_bytes,
+                       M, m->plan.precision, s);
   UML_HIP_CHECK(hipGetLastError());
   return UML_OK;
 }

@@ -10,7 +10,6 @@
 namespace uml {
 
 constexpr int kMaxPairs = UML_MAX_PARAMS * (UML_MAX_PARAMS + 1) / 2;
-constexpr int kHessSumsPerThread = (1 + UML_MAX_PARAMS + 2 * kMaxPairs + kBlock - 1) / kBlock;
 
 // Relation of a parameter pair (a, b) within one component (HessPlan::rel):
 // index >= 0 of the unit's own d2p/p entry, or one of these.
@@ -43,6 +42,7 @@ struct HessArgs {
   int chunk;               // events staged at once
   int row_len;             // staged values per event
   int n_sums;              // 1 + nfree + 2 npairs
+  int mat_bytes;           // LDS for a tile's matrix and vector sums
 };
 
 // One dataset of a batched Hessian pass: its arguments, its parameter vector
@@ -57,13 +57,14 @@ struct HessJob {
 // parameter appears in two units of one component.
 bool build_hess_plan(const Plan& P, HessPlan& H, std::string& err);
 int hess_row_len(const Plan& P, const HessPlan& H);
-size_t hess_lds_bytes(int row_len, int chunk, int precision);
+size_t hess_lds_bytes(int row_len, int chunk, int precision, int mat_bytes);
+int hess_mat_bytes(const Plan& P, const HessPlan& H);
 void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, double* d_hc,
                     double* d_out, int precision, hipStream_t s);
 // Batched pass over n_jobs datasets of one model: d_map holds n_map (job,
 // tile) entries (job < 0: padding); row_len, chunk and n_sums are the
 // model's.
 void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, int n_map, int row_len,
-                          int chunk, int n_sums, int precision, hipStream_t s);
+                          int chunk, int mat_bytes, int n_sums, int precision, hipStream_t s);
 
 }  // namespace uml

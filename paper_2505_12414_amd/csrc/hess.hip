@@ -226,7 +226,28 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
   }
 }
 
+typedef double hess_d4 __attribute__((ext_vector_type(4)));
+
+// The matrix sums of a tile, over the free parameters padded to 16 or 32:
+//   product 0: sum w s s^T,  product 1: sum w^2 s s^T,
+//   product 2 + c: sum w r_c l_c l_c^T (component c),
+// each as 1 or 2 x 2 blocks of 16 x 16 (block b: rows 16 (b >> 1), columns
+// 16 (b & 1)).  Product p belongs to wave p % 4.
+static_assert(kBlock == 256, "the Hessian tile assigns its matrix products to four waves");
+constexpr int kHessProdPerWave = (2 + kMaxComp + 3) / 4;
+
 // One tile of one dataset: its M sums go to A.part[j * A.n_tiles + tile].
+// Per chunk, the staged rows feed
+//   * the vector sums (one thread each): sum w log2 P, sum w s_a, and
+//     sum w r_c q_k for every second-derivative entry k of a factor of c;
+//   * the matrix sums on the FP64 matrix cores (v_mfma_f64_16x16x4f64: four
+//     events per instruction; lane l supplies row l % 16 of the left operand
+//     and column l % 16 of the right one for event l / 16, and holds outputs
+//     (l / 16 + 4 i, l % 16), i < 4).
+// At the end of the tile the pairs are assembled from them:
+//   H_ab  = (sum w s s^T)_ab - sum_c [l_a l_b of c if a and b are in different
+//           units of c; sum w r_c q of their unit if in the same one; else 0],
+//   W2_ab = (sum w^2 s s^T)_ab.
 template <class T>
 __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -252,8 +273,42 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
   const Plan& P = *sP;
   const HessPlan& H = *sH;
   const int nf = P.nfree, nc = P.ncomp, V = A.row_len, M = A.n_sums;
-  double acc[kHessSumsPerThread];
-  for (int k = 0; k < kHessSumsPerThread; ++k) acc[k] = 0.0;
+  const int lane = tid & 63;
+  const int nb = nf > 16 ? 2 : 1;
+  const int nvec = 1 + nf + H.nq;
+  const int r_off = 2 + nf, l_off = 2 + nf + nc, q_off = 2 + nf + nc + nc * nf;
+  // this thread's vector sum: the staged value it weights, and the
+  // responsibility it is multiplied by (-1: none)
+  int voff = -1, vr = -1;
+  if (tid == 0) {
+    voff = 1;
+  } else if (tid <= nf) {
+    voff = 2 + tid - 1;
+  } else if (tid < nvec) {
+    const int k = tid - 1 - nf;
+    int fi = 0;  // the factor of entry k: the last with q_off <= k
+    while (fi + 1 < P.nfac && H.q_off[fi + 1] <= k) ++fi;
+    int comp = 0;
+    for (int c = 0; c < nc; ++c)
+      for (int j = 0; j < P.comp[c].nfac; ++j)
+        if (P.comp[c].fac[j] == fi) comp = c;
+    voff = q_off + k;
+    vr = r_off + comp;
+  }
+  double vacc = 0.0;
+  // this wave's products (wave w takes products w and w + 4), each with its
+  // nb x nb accumulator blocks; the wave index is made uniform explicitly so
+  // the choice of operands is a scalar branch
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nprod = 2 + nc;
+  const int kq = lane >> 4, iq = lane & 15;
+  const bool o0 = iq < nf, o1 = iq + 16 < nf;
+  const int i0 = o0 ? iq : 0, i1 = o1 ? iq + 16 : 0;
+  hess_d4 macc[kHessProdPerWave][4];
+#pragma unroll
+  for (int u = 0; u < kHessProdPerWave; ++u)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) macc[u][b] = hess_d4{0.0, 0.0, 0.0, 0.0};
   const int64_t t0 = int64_t(tile) * A.tile_events;
   const int64_t t1 = t0 + A.tile_events < A.n ? t0 + A.tile_events : A.n;
   for (int64_t c0 = t0; c0 < t1; c0 += A.chunk) {
@@ -264,46 +319,117 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
       hess_event<T>(A, P, *sC, sh, H, c0 + tid, row);
     }
     __syncthreads();
-    for (int k = 0; k < kHessSumsPerThread; ++k) {
-      const int j = tid + k * kBlock;
-      if (j >= M) break;
-      double sacc = 0.0;
-      if (j == 0) {
-        for (int e = 0; e < cnt; ++e) sacc += double(stage[e * V]) * double(stage[e * V + 1]);
-      } else if (j <= nf) {
-        for (int e = 0; e < cnt; ++e) sacc += double(stage[e * V]) * double(stage[e * V + 2 + j - 1]);
-      } else {
-        const int pr = (j - 1 - nf) % H.npairs;
-        const bool w2 = (j - 1 - nf) >= H.npairs;
-        const int a = H.pa[pr], b = H.pb[pr];
-        const signed char* rel = H.rel + pr * kMaxComp;
-        for (int e = 0; e < cnt; ++e) {
-          const T* row = stage + e * V;
-          const double w = double(row[0]);
-          const double ss = double(row[2 + a]) * double(row[2 + b]);
-          if (w2) {
-            sacc += w * w * ss;
-            continue;
+    if (tid < nvec) {  // four events per step, four partial sums combined in a fixed order
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      const int vo = vr >= 0 ? vr : 0;
+      int e = 0;
+#pragma unroll 2
+      for (; e + 4 <= cnt; e += 4) {
+        const T* r0 = stage + e * V;
+        const T* r1 = r0 + V;
+        const T* r2 = r1 + V;
+        const T* r3 = r2 + V;
+        double v0 = double(r0[0]) * double(r0[voff]), v1 = double(r1[0]) * double(r1[voff]);
+        double v2 = double(r2[0]) * double(r2[voff]), v3 = double(r3[0]) * double(r3[voff]);
+        if (vr >= 0) {
+          v0 *= double(r0[vo]);
+          v1 *= double(r1[vo]);
+          v2 *= double(r2[vo]);
+          v3 *= double(r3[vo]);
+        }
+        p0 += v0;
+        p1 += v1;
+        p2 += v2;
+        p3 += v3;
+      }
+      for (; e < cnt; ++e) {
+        const T* r0 = stage + e * V;
+        const double v0 = double(r0[0]) * double(r0[voff]);
+        p0 += vr >= 0 ? v0 * double(r0[vo]) : v0;
+      }
+      vacc += (p0 + p1) + (p2 + p3);
+    }
+    // matrix sums: per step every lane loads the staged values of its event
+    // that this wave's products use (at parameters iq and iq + 16)
+    for (int e0 = 0; e0 < cnt; e0 += 4) {
+      const int e = e0 + kq;
+      const bool ev = e < cnt;
+      const T* row = stage + (ev ? e : 0) * V;
+      const double w = ev ? double(row[0]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < kHessProdPerWave; ++u) {
+        const int pr = wv + 4 * u;
+        if (pr < nprod) {  // uniform
+          double x0, x1, sc;
+          if (pr < 2) {
+            x0 = (ev && o0) ? double(row[2 + i0]) : 0.0;
+            x1 = (ev && o1) ? double(row[2 + i1]) : 0.0;
+            sc = pr == 0 ? w : w * w;
+          } else {
+            const int c = pr - 2;
+            const T* l = row + l_off + c * nf;
+            x0 = (ev && o0) ? double(l[i0]) : 0.0;
+            x1 = (ev && o1) ? double(l[i1]) : 0.0;
+            sc = w * double(row[r_off + c]);
           }
-          double d2 = 0.0;  // sum_c r_c (d2 S_c / S_c)_ab
-          for (int c = 0; c < nc; ++c) {
-            const int rc = rel[c];
-            if (rc == kRelAbsent || rc == kRelZero) continue;
-            const double rv = double(row[2 + nf + c]);
-            const T* l = row + 2 + nf + nc + c * nf;
-            d2 += rv * (rc == kRelProduct ? double(l[a]) * double(l[b])
-                                          : double(row[2 + nf + nc + nc * nf + rc]));
+          const double a0 = x0 * sc;
+          macc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, macc[u][0], 0, 0, 0);
+          if (nb == 2) {
+            const double a1 = x1 * sc;
+            macc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, macc[u][1], 0, 0, 0);
+            macc[u][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0, macc[u][2], 0, 0, 0);
+            macc[u][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, macc[u][3], 0, 0, 0);
           }
-          sacc += w * (ss - d2);
         }
       }
-      acc[k] += sacc;
     }
     __syncthreads();
   }
-  for (int k = 0; k < kHessSumsPerThread; ++k) {
-    const int j = tid + k * kBlock;
-    if (j < M) A.part[int64_t(j) * A.n_tiles + tile] = acc[k];
+  // the tile's sums to LDS (over the staging rows): [2 + nc][nf][nf], then the
+  // vector sums
+  double* mats = reinterpret_cast<double*>(stage);
+  double* vs = mats + (2 + nc) * nf * nf;
+#pragma unroll
+  for (int u = 0; u < kHessProdPerWave; ++u) {
+    const int pr = wv + 4 * u;
+    if (pr < nprod) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if (b >= nb * nb) break;
+        const int col = (b & 1) * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rw = (b >> 1) * 16 + (lane >> 4) + 4 * i;
+          if (rw < nf && col < nf) mats[(pr * nf + rw) * nf + col] = macc[u][b][i];
+        }
+      }
+    }
+  }
+  if (tid < nvec) vs[tid] = vacc;
+  __syncthreads();
+  for (int j = tid; j < M; j += kBlock) {
+    double o;
+    if (j <= nf) {
+      o = vs[j];
+    } else {
+      const int pr = (j - 1 - nf) % H.npairs;
+      const bool w2 = (j - 1 - nf) >= H.npairs;
+      const int a = H.pa[pr], b = H.pb[pr];
+      if (w2) {
+        o = mats[(nf + a) * nf + b];
+      } else {
+        double d2 = 0.0;  // sum_c of w r_c (d2 S_c / S_c)_ab
+        for (int c = 0; c < nc; ++c) {
+          const int rc = H.rel[pr * kMaxComp + c];
+          if (rc == kRelProduct)
+            d2 += mats[((2 + c) * nf + a) * nf + b];
+          else if (rc >= 0)
+            d2 += vs[1 + nf + rc];
+        }
+        o = mats[a * nf + b] - d2;
+      }
+    }
+    A.part[int64_t(j) * A.n_tiles + tile] = o;
   }
 }
 
@@ -319,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void hess_batch_kernel(const HessJob* __res
                                                             const int2* __restrict__ tmap) {
   const int2 t = tmap[blockIdx.x];
   if (t.x < 0) return;
-  const HessArgs A = jobs[t.x].A;
+  const HessArgs& A = jobs[t.x].A;  // read in place: the column table is indexed at run time
   hess_tile<T>(A, t.y);
 }
 
@@ -350,15 +476,20 @@ __global__ __launch_bounds__(kBlock) void hess_reduce_batch_kernel(const HessJob
   if (j < J.A.n_sums) hess_reduce(J.A.part, J.A.n_tiles, j, J.out);
 }
 
-size_t hess_lds_bytes(int row_len, int chunk, int precision) {
+size_t hess_lds_bytes(int row_len, int chunk, int precision, int mat_bytes) {
+  const size_t stage = size_t(row_len) * chunk * (precision == UML_MIXED ? 4 : 8);
   return sizeof(Plan) + sizeof(ConstBlock) + sizeof(HessPlan) + sizeof(double) * 4 * kMaxFac +
-         size_t(row_len) * chunk * (precision == UML_MIXED ? 4 : 8);
+         (stage > size_t(mat_bytes) ? stage : size_t(mat_bytes));
+}
+
+int hess_mat_bytes(const Plan& P, const HessPlan& H) {
+  return int(sizeof(double)) * ((2 + P.ncomp) * P.nfree * P.nfree + 1 + P.nfree + H.nq);
 }
 
 void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, double* d_hc,
                     double* d_out, int precision, hipStream_t s) {
   hipLaunchKernelGGL(hess_prologue_kernel, dim3(1), dim3(256), 0, s, A.plan, d_theta, d_cb, d_hc);
-  const size_t lds = hess_lds_bytes(A.row_len, A.chunk, precision);
+  const size_t lds = hess_lds_bytes(A.row_len, A.chunk, precision, A.mat_bytes);
   if (precision == UML_MIXED)
     hipLaunchKernelGGL(hess_kernel<float>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
   else
@@ -368,10 +499,10 @@ void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, 
 }
 
 void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, int n_map, int row_len,
-                          int chunk, int n_sums, int precision, hipStream_t s) {
+                          int chunk, int mat_bytes, int n_sums, int precision, hipStream_t s) {
   if (n_jobs <= 0) return;
   hipLaunchKernelGGL(hess_prologue_batch_kernel, dim3(n_jobs), dim3(256), 0, s, d_jobs);
-  const size_t lds = hess_lds_bytes(row_len, chunk, precision);
+  const size_t lds = hess_lds_bytes(row_len, chunk, precision, mat_bytes);
   if (precision == UML_MIXED)
     hipLaunchKernelGGL(hess_batch_kernel<float>, dim3(n_map), dim3(kBlock), lds, s, d_jobs, d_map);
   else
