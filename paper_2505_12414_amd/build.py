@@ -24,7 +24,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 # registers, which would otherwise add to every event kernel's register count
 # and cost it a wave per SIMD.
 HIP_FLAGS = ["-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
-SOURCES = ["eval.hip", "hess.hip", "gen.hip", "model.cpp", "api.cpp", "fit.cpp", "server.cpp"]
+SOURCES = ["eval.hip", "hess.hip", "gen.hip", "scatter.hip", "model.cpp", "api.cpp", "fit.cpp", "server.cpp"]
 
 
 def _compile(src, verbose):

@@ -154,21 +154,26 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
   J.npar = P.npar;
 }
 
+// The precomputed event-only terms of a model that stores them (nothing
+// otherwise), from the dataset's event columns.
+hipError_t data_precompute(uml_data* d, hipStream_t s) {
+  const Plan& P = d->model->plan;
+  if (P.pre_fac < 0 || d->n <= 0) return hipSuccess;
+  const FactorPlan& F = P.fac[P.pre_fac];
+  PrecomputeArgs a{};
+  for (int k = 0; k < 3; ++k) a.in[k] = d->job.col[F.dim[k]];
+  for (int k = 0; k < kPWaveTerms; ++k) a.out[k] = const_cast<void*>(d->job.col[F.pre + k]);
+  a.n = d->n;
+  launch_pwave_terms(a, P.precision, s);
+  return hipGetLastError();
+}
+
 // The work area of a freshly placed dataset: counters and caches cleared,
 // the job descriptor copied.
 hipError_t data_init_work(uml_data* d, const DataLayout& L, hipStream_t s) {
-  const Plan& P = d->model->plan;
-  if (P.pre_fac >= 0 && d->n > 0) {  // the precomputed event-only terms
-    const FactorPlan& F = P.fac[P.pre_fac];
-    PrecomputeArgs a{};
-    for (int k = 0; k < 3; ++k) a.in[k] = d->job.col[F.dim[k]];
-    for (int k = 0; k < kPWaveTerms; ++k) a.out[k] = const_cast<void*>(d->job.col[F.pre + k]);
-    a.n = d->n;
-    launch_pwave_terms(a, P.precision, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipError_t e = hipMemsetAsync(d->d_work, 0, L.o_part, s);
+  hipError_t e = data_precompute(d, s);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(d->d_work, 0, L.o_part, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &d->job, sizeof(Job), hipMemcpyHostToDevice, s);
   return e;
 }

@@ -449,30 +449,39 @@ __global__ __launch_bounds__(kBlock) void hess_batch_kernel(const HessJob* __res
   hess_tile<T>(A, t.y);
 }
 
-// Sum j of every tile, in tile order (Neumaier).
+// Sum j of every tile, by one wave: lane l adds tiles l, l + 64, .. in order
+// (Neumaier), then the 64 lane sums are added in a fixed tree.  The order
+// depends only on the tile count, so the result is reproducible.
 __device__ __forceinline__ void hess_reduce(const double* __restrict__ part, int n_tiles, int j,
                                             double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
   const double* col = part + int64_t(j) * n_tiles;
   double s = 0.0, comp = 0.0;
-  for (int t = 0; t < n_tiles; ++t) {
+  for (int t = lane; t < n_tiles; t += 64) {
     const double x = col[t];
     const double u = s + x;
     comp += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
     s = u;
   }
-  out[j] = s + comp;
+  double v = s + comp;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if (lane == 0) out[j] = v;
 }
+
+// Four sums per workgroup (one per wave).
+constexpr int kReduceSumsPerBlock = kBlock / 64;
 
 __global__ __launch_bounds__(kBlock) void hess_reduce_kernel(const double* __restrict__ part, int n_tiles,
                                                              int M, double* __restrict__ out) {
-  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int j = blockIdx.x * kReduceSumsPerBlock + int(threadIdx.x >> 6);
   if (j < M) hess_reduce(part, n_tiles, j, out);
 }
 
 // A batch: blockIdx.y is the job.
 __global__ __launch_bounds__(kBlock) void hess_reduce_batch_kernel(const HessJob* __restrict__ jobs) {
   const HessJob& J = jobs[blockIdx.y];
-  const int j = blockIdx.x * kBlock + threadIdx.x;
+  const int j = blockIdx.x * kReduceSumsPerBlock + int(threadIdx.x >> 6);
   if (j < J.A.n_sums) hess_reduce(J.A.part, J.A.n_tiles, j, J.out);
 }
 
@@ -494,8 +503,8 @@ void launch_hessian(const HessArgs& A, const double* d_theta, ConstBlock* d_cb, 
     hipLaunchKernelGGL(hess_kernel<float>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
   else
     hipLaunchKernelGGL(hess_kernel<double>, dim3(A.n_tiles), dim3(kBlock), lds, s, A);
-  hipLaunchKernelGGL(hess_reduce_kernel, dim3((A.n_sums + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     A.part, A.n_tiles, A.n_sums, d_out);
+  hipLaunchKernelGGL(hess_reduce_kernel, dim3((A.n_sums + kReduceSumsPerBlock - 1) / kReduceSumsPerBlock),
+                     dim3(kBlock), 0, s, A.part, A.n_tiles, A.n_sums, d_out);
 }
 
 void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, int n_map, int row_len,
@@ -507,8 +516,9 @@ void launch_hessian_batch(const HessJob* d_jobs, int n_jobs, const int2* d_map, 
     hipLaunchKernelGGL(hess_batch_kernel<float>, dim3(n_map), dim3(kBlock), lds, s, d_jobs, d_map);
   else
     hipLaunchKernelGGL(hess_batch_kernel<double>, dim3(n_map), dim3(kBlock), lds, s, d_jobs, d_map);
-  hipLaunchKernelGGL(hess_reduce_batch_kernel, dim3((n_sums + kBlock - 1) / kBlock, n_jobs), dim3(kBlock), 0,
-                     s, d_jobs);
+  hipLaunchKernelGGL(hess_reduce_batch_kernel,
+                     dim3((n_sums + kReduceSumsPerBlock - 1) / kReduceSumsPerBlock, n_jobs), dim3(kBlock), 0, s,
+                     d_jobs);
 }
 
 }  // namespace uml

@@ -58,6 +58,9 @@ std::string plan_describe(const Plan& P);
 // thread-local error message
 int set_error(int code, const std::string& msg);
 
+// The precomputed event-only terms of a model that stores them (no-op otherwise).
+hipError_t data_precompute(uml_data* d, hipStream_t s);
+
 // Event storage and work-area layout of a dataset.
 struct DataLayout {
   int E, n_tiles;

@@ -1,0 +1,28 @@
+// Packed host<->device transfers for the serving loop: many small pieces for
+// many destinations travel in one copy and are placed (or collected) by one
+// kernel, instead of one copy each.  Every copy is a separate stream
+// operation with a fixed cost of its own, which dominated admitting and
+// retiring fits one small copy at a time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace uml {
+
+// One piece: nbytes (a multiple of 8, 8-byte aligned at both ends) between
+// the device address `ptr` and offset `off` of a staging buffer.  For an
+// upload, off < 0 writes zeros instead.
+struct PackRec {
+  void* ptr;
+  int64_t off;
+  int64_t nbytes;
+};
+
+// staging -> pieces; one workgroup per record
+void launch_scatter(const PackRec* d_recs, int n, const void* d_staging, hipStream_t s);
+// pieces -> staging; one workgroup per record
+void launch_gather(const PackRec* d_recs, int n, void* d_staging, hipStream_t s);
+
+}  // namespace uml

@@ -1,0 +1,43 @@
+// Placement kernels of the packed transfers (see scatter.h).
+#include <hip/hip_runtime.h>
+
+#include "scatter.h"
+
+namespace uml {
+namespace {
+
+__global__ __launch_bounds__(256) void scatter_kernel(const PackRec* __restrict__ recs,
+                                                      const uint64_t* __restrict__ staging) {
+  const PackRec r = recs[blockIdx.x];
+  uint64_t* dst = static_cast<uint64_t*>(r.ptr);
+  const int64_t n = r.nbytes / 8;
+  if (r.off < 0) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = 0;
+  } else {
+    const uint64_t* src = staging + r.off / 8;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const PackRec* __restrict__ recs,
+                                                     uint64_t* __restrict__ staging) {
+  const PackRec r = recs[blockIdx.x];
+  const uint64_t* src = static_cast<const uint64_t*>(r.ptr);
+  uint64_t* dst = staging + r.off / 8;
+  const int64_t n = r.nbytes / 8;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+}  // namespace
+
+void launch_scatter(const PackRec* d_recs, int n, const void* d_staging, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(256), 0, s, d_recs, static_cast<const uint64_t*>(d_staging));
+}
+
+void launch_gather(const PackRec* d_recs, int n, void* d_staging, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gather_kernel, dim3(n), dim3(256), 0, s, d_recs, static_cast<uint64_t*>(d_staging));
+}
+
+}  // namespace uml

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "host.h"
+#include "scatter.h"
 
 namespace uml {
 
@@ -120,6 +121,59 @@ struct SlotHost {
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Packed uploads (scatter.h): pieces staged in one pinned buffer, sent with
+// one copy per flush and placed by one kernel.  A flushed range stays in use
+// until the stream has passed it, so the buffer starts over only after a
+// synchronisation (reset).
+struct Packer {
+  char* h = nullptr;  // pinned
+  char* d = nullptr;  // device
+  size_t cap = 0, start = 0, used = 0;
+  std::vector<PackRec> recs;
+  bool unsynced = false;
+
+  static size_t up8(size_t x) { return (x + 7) & ~size_t(7); }
+  static size_t up16(size_t x) { return (x + 15) & ~size_t(15); }
+  bool room(size_t payload) const {
+    return up16(used + payload) + (recs.size() + 1) * sizeof(PackRec) <= cap;
+  }
+  // nbytes: a multiple of 8 (every piece here is made of 8-byte words)
+  bool put(void* dst, const void* src, size_t nbytes) {
+    if (nbytes % 8 || !room(nbytes)) return false;
+    std::memcpy(h + used, src, nbytes);
+    recs.push_back(PackRec{dst, int64_t(used - start), int64_t(nbytes)});
+    used += nbytes;
+    return true;
+  }
+  bool zero(void* dst, size_t nbytes) {
+    if (nbytes % 8 || !room(0)) return false;
+    recs.push_back(PackRec{dst, -1, int64_t(nbytes)});
+    return true;
+  }
+  hipError_t flush(hipStream_t s) {
+    if (recs.empty()) return hipSuccess;
+    const size_t ro = up16(used);
+    std::memcpy(h + ro, recs.data(), recs.size() * sizeof(PackRec));
+    const size_t end = ro + recs.size() * sizeof(PackRec);
+    hipError_t e = hipMemcpyAsync(d + start, h + start, end - start, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      launch_scatter(reinterpret_cast<const PackRec*>(d + ro), int(recs.size()), d + start, s);
+      e = hipGetLastError();
+    }
+    start = used = up16(end);
+    recs.clear();
+    unsynced = true;
+    return e;
+  }
+  hipError_t reset(hipStream_t s) {
+    const hipError_t e = unsynced ? hipStreamSynchronize(s) : hipSuccess;
+    start = used = 0;
+    recs.clear();
+    unsynced = false;
+    return e;
+  }
+};
+
 // Grid sizes the batched iteration is captured for: the active fits' tiles,
 // rounded up to the next size of a geometric ladder (ratio about 1.19), so a
 // changing active set reuses a few captured graphs; the padding tiles exit
@@ -183,6 +237,12 @@ struct uml_server {
   GenJob* d_genjobs = nullptr;
   int2* h_genmap = nullptr;
   int2* d_genmap = nullptr;
+  // packed uploads of admission, and the packed fit states of retirement
+  Packer up;
+  PackRec* h_grecs = nullptr;
+  PackRec* d_grecs = nullptr;
+  char* h_gst = nullptr;
+  char* d_gst = nullptr;
   std::vector<Slot> slots;
   std::vector<Job> jobs;
   std::map<int, CapturedGraph> graphs;  // by grid bucket
@@ -234,9 +294,19 @@ struct Intake {
 // uploads its events, queues the Hessian pass at its start point (the start
 // metric), waits once for the whole batch, then writes the fit states.  A
 // request whose start point has P <= 0 somewhere is answered at once.
+// The packed form of data_init_work plus the start point: the job, the
+// cleared constant cache, counters and outputs, and theta (padded with zeros).
+bool pack_init(Packer& up, const uml_data& d, const DataLayout& L, const double* theta_padded) {
+  char* w = static_cast<char*>(d.d_work);
+  return up.put(w + L.o_job, &d.job, sizeof(Job)) && up.zero(w + L.o_cst, L.o_theta - L.o_cst) &&
+         up.put(w + L.o_theta, theta_padded, sizeof(double) * UML_MAX_PARAMS) &&
+         up.zero(w + L.o_out, L.o_part - L.o_out);
+}
+
 int admit_batch(uml_server* S, std::vector<Intake>& in) {
   const uml_model* m = S->m;
   const int ns = int(S->slots.size());
+  UML_HIP_CHECK(S->up.reset(S->stream));
   UML_HIP_CHECK(hipMemsetAsync(S->d_genbad, 0, sizeof(unsigned int) * ns, S->stream));
   int n_gen = 0, n_gmap = 0;  // requests drawn on the device, in one batched launch
   for (auto& it : in) {
@@ -257,9 +327,10 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     SlotHost& H = S->h_slots[it.slot];
     hipError_t e = hipSuccess;
     if (sl.req.generate) {  // drawn below; until then the output area holds the point
+      std::memset(H.gen_theta, 0, sizeof(H.gen_theta));
       std::memcpy(H.gen_theta, sl.req.gen_theta.data(), sizeof(double) * m->plan.npar);
-      e = hipMemcpyAsync(sl.data.d_out, H.gen_theta, sizeof(double) * m->plan.npar, hipMemcpyHostToDevice,
-                         S->stream);
+      if (!S->up.put(sl.data.d_out, H.gen_theta, sizeof(double) * UML_MAX_PARAMS))
+        return set_error(UML_E_INVALID, "server: upload staging full");
       S->h_genjobs[n_gen] = GenJob{gen_out(&sl.data, S->d_genbad + it.slot), sl.data.d_out, sl.req.seed};
       for (int64_t b = 0; b * 256 < sl.req.n; ++b) {
         if (n_gmap >= S->hmap_cap) return set_error(UML_E_INVALID, "server: generation map full");
@@ -267,30 +338,31 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
       }
       ++n_gen;
     } else {
-      e = data_upload(&sl.data, sl.layout, sl.req.host, S->stream);
+      e = hipMemcpyAsync(sl.data.d_events, sl.req.host.data(), sl.req.host.size(), hipMemcpyHostToDevice,
+                         S->stream);
     }
     if (e != hipSuccess) return set_error(UML_E_HIP, std::string("server upload: ") + hipGetErrorString(e));
   }
-  if (n_gen) {  // one launch draws every generated request; then their work areas
+  if (n_gen) {  // one launch draws every generated request (their points placed first)
+    UML_HIP_CHECK(S->up.flush(S->stream));
     UML_HIP_CHECK(hipMemcpyAsync(S->d_genjobs, S->h_genjobs, sizeof(GenJob) * n_gen, hipMemcpyHostToDevice,
                                  S->stream));
     UML_HIP_CHECK(hipMemcpyAsync(S->d_genmap, S->h_genmap, sizeof(int2) * n_gmap, hipMemcpyHostToDevice,
                                  S->stream));
     launch_generate_batch(m->d_gplan, S->d_genjobs, S->d_genmap, n_gmap, m->plan.precision, S->stream);
     UML_HIP_CHECK(hipGetLastError());
-    for (auto& it : in) {
-      Slot& sl = S->slots[it.slot];
-      if (sl.req.generate) UML_HIP_CHECK(data_init_work(&sl.data, sl.layout, S->stream));
-    }
   }
-  // start points, once every work area is initialised (which clears them)
+  // every work area initialised, start points included, in one packed upload
   for (auto& it : in) {
     Slot& sl = S->slots[it.slot];
     SlotHost& H = S->h_slots[it.slot];
+    UML_HIP_CHECK(data_precompute(&sl.data, S->stream));
+    std::memset(H.theta, 0, sizeof(H.theta));
     std::memcpy(H.theta, sl.req.start.data(), sizeof(double) * m->plan.npar);
-    UML_HIP_CHECK(hipMemcpyAsync(sl.data.d_theta, H.theta, sizeof(double) * m->plan.npar,
-                                 hipMemcpyHostToDevice, S->stream));
+    if (!pack_init(S->up, sl.data, sl.layout, H.theta))
+      return set_error(UML_E_INVALID, "server: upload staging full");
   }
+  UML_HIP_CHECK(S->up.flush(S->stream));
   const int nb = int(in.size()), M = hess_sums(m);
   std::vector<uml_data*> ds(nb);
   std::vector<const double*> th(nb);
@@ -341,11 +413,12 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     J.theta = S->d_fs[i].theta;
     J.out = S->d_fs[i].out;
     S->jobs[i] = J;
-    UML_HIP_CHECK(hipMemcpyAsync(S->d_fs + i, &H.fs, sizeof(FitState), hipMemcpyHostToDevice, S->stream));
-    UML_HIP_CHECK(hipMemcpyAsync(S->d_jobs + i, &S->jobs[i], sizeof(Job), hipMemcpyHostToDevice, S->stream));
+    if (!S->up.put(S->d_fs + i, &H.fs, sizeof(FitState)) || !S->up.put(S->d_jobs + i, &S->jobs[i], sizeof(Job)))
+      return set_error(UML_E_INVALID, "server: upload staging full");
     std::lock_guard<std::mutex> lk(S->mu);
     S->active++;
   }
+  UML_HIP_CHECK(S->up.flush(S->stream));  // the fit states and jobs of the admitted fits
   return UML_OK;
 }
 
@@ -358,9 +431,13 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
   const Plan& P = m->plan;
   const bool polish = S->opt.fit.polish > 0;
   const int nb = int(fin.size()), M = hess_sums(m);
-  for (int i : fin)
-    UML_HIP_CHECK(hipMemcpyAsync(&S->h_slots[i].fs, S->d_fs + i, sizeof(FitState), hipMemcpyDeviceToHost,
-                                 S->stream));
+  // the finished fit states, collected by one kernel and one copy
+  for (int j = 0; j < nb; ++j)
+    S->h_grecs[j] = PackRec{S->d_fs + fin[j], int64_t(sizeof(FitState)) * j, int64_t(sizeof(FitState))};
+  UML_HIP_CHECK(hipMemcpyAsync(S->d_grecs, S->h_grecs, sizeof(PackRec) * nb, hipMemcpyHostToDevice, S->stream));
+  launch_gather(S->d_grecs, nb, S->d_gst, S->stream);
+  UML_HIP_CHECK(hipGetLastError());
+  UML_HIP_CHECK(hipMemcpyAsync(S->h_gst, S->d_gst, sizeof(FitState) * nb, hipMemcpyDeviceToHost, S->stream));
   if (!polish) {  // the Hessian pass at each final point, read on the device
     std::vector<uml_data*> ds(nb);
     std::vector<const double*> th(nb);
@@ -375,6 +452,8 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
                                  S->stream));
   }
   UML_HIP_CHECK(hipStreamSynchronize(S->stream));
+  for (int j = 0; j < nb; ++j)
+    std::memcpy(&S->h_slots[fin[j]].fs, S->h_gst + sizeof(FitState) * j, sizeof(FitState));
   for (int j = 0; j < nb; ++j) {
     const int i = fin[j];
     Slot& sl = S->slots[i];
@@ -439,8 +518,11 @@ void free_server_memory(uml_server* S) {
   for (void* p : {static_cast<void*>(S->h_slots), static_cast<void*>(S->h_done),
                   static_cast<void*>(S->h_hjobs), static_cast<void*>(S->h_hmap),
                   static_cast<void*>(S->h_hsums), static_cast<void*>(S->h_genbad),
-                  static_cast<void*>(S->h_genjobs), static_cast<void*>(S->h_genmap)})
+                  static_cast<void*>(S->h_genjobs), static_cast<void*>(S->h_genmap),
+                  static_cast<void*>(S->up.h), static_cast<void*>(S->h_grecs), static_cast<void*>(S->h_gst)})
     if (p) (void)hipHostFree(p);
+  for (void* p : {static_cast<void*>(S->up.d), static_cast<void*>(S->d_grecs), static_cast<void*>(S->d_gst)})
+    if (p) (void)hipFree(p);
   if (S->stream) (void)hipStreamDestroy(S->stream);
 }
 
@@ -635,6 +717,19 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genmap), sizeof(int2) * size_t(S->hmap_cap),
                       hipHostMallocDefault);
+  // packed transfers: every piece one admission batch uploads (fit state,
+  // two jobs, two parameter vectors per request, their records and padding),
+  // and the fit states one retirement batch collects
+  S->up.cap = size_t(ns) * (sizeof(FitState) + 2 * sizeof(Job) + 2 * sizeof(double) * UML_MAX_PARAMS +
+                            8 * sizeof(PackRec)) + (64 << 10);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->up.h), S->up.cap, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->up.d), S->up.cap);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_grecs), sizeof(PackRec) * ns, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_grecs), sizeof(PackRec) * ns);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_gst), sizeof(FitState) * ns, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_gst), sizeof(FitState) * ns);
   if (e != hipSuccess) return fail(e, "pinned staging");
   S->arena.init(static_cast<char*>(S->arena_mem), size_t(S->opt.hbm_budget));
   S->d_fs = reinterpret_cast<FitState*>(S->state_mem);
