@@ -981,6 +981,8 @@ static const Family* families() {
       make_family<Shape<Comp<Cheb<0, 4>>>>(),
       make_family<Shape<Comp<PWave<0, 1, 2>>>>(),                            // angular fit
       make_family<Shape<Comp<Exp<0>>, Comp<Gauss<0>>>>(),                    // mass fit
+      make_family<Shape<Comp<Exp<0>>, Comp<Gauss<0>>, Comp<Gauss<0>>>>(),    // two peaks + background
+      make_family<Shape<Comp<Cheb<0, 1>>, Comp<Exp<0>>, Comp<Gauss<0>>, Comp<Gauss<0>>>>(),
       make_family<Shape<Comp<Gauss<0>, PWave<1, 2, 3>>>>(),                  // 4-D signal
       make_family<Shape<Comp<Exp<0>, Cheb<1, 2>, Cheb<2, 2>, Cheb<3, 2>>,  // 4-D model
                         Comp<Gauss<0>, PWave<1, 2, 3>>>>(),

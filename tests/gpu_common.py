@@ -49,6 +49,29 @@ def sig4d_desc():
             "root": 2}
 
 
+def mix_desc(ncomp):
+    """A 1-D mixture of 3 or 4 components as nested sums: two Gaussians, an
+    exponential and (for 4) a Chebyshev series, on [5.0, 5.6]."""
+    params = [{"name": "mu1", "value": 5.25}, {"name": "s1", "value": 0.02},
+              {"name": "mu2", "value": 5.35}, {"name": "s2", "value": 0.04},
+              {"name": "lambda", "value": -1.5},
+              {"name": "f1", "value": 0.3}, {"name": "f2", "value": 0.4}]
+    nodes = [{"kind": "gauss", "dims": [0], "params": [0, 1]},
+             {"kind": "gauss", "dims": [0], "params": [2, 3]},
+             {"kind": "exp", "dims": [0], "params": [4]}]
+    if ncomp == 3:
+        nodes += [{"kind": "sum", "children": [1, 2], "params": [6]},
+                  {"kind": "sum", "children": [0, 3], "params": [5]}]
+    else:
+        params += [{"name": "c1", "value": 0.2}, {"name": "f3", "value": 0.5}]
+        nodes += [{"kind": "cheb", "dims": [0], "params": [7]},
+                  {"kind": "sum", "children": [2, 3], "params": [8]},
+                  {"kind": "sum", "children": [1, 4], "params": [6]},
+                  {"kind": "sum", "children": [0, 5], "params": [5]}]
+    return {"dims": [{"name": "m", "lo": 5.0, "hi": 5.6}], "params": params, "nodes": nodes,
+            "root": len(nodes) - 1}
+
+
 def rng_events(desc, n, seed, dtype):
     """Seeded events for any description (the generators for the workload
     models, uniform points inside the ranges otherwise)."""

@@ -7,7 +7,8 @@ import oracle
 from paper_2505_12414_amd import uml
 from paper_2505_12414_amd import workloads as W
 
-from gpu_common import cheb_desc, exp_desc, gauss_desc, random_points, rng_events, say, sig4d_desc, sigmas
+from gpu_common import (cheb_desc, exp_desc, gauss_desc, mix_desc, random_points, rng_events, say,
+                        sig4d_desc, sigmas)
 
 pytestmark = pytest.mark.gpu
 
@@ -47,7 +48,7 @@ def test_hessian_matches_oracle(name, mk, n, precision):
         nll_g, g_g, h_g = uml.uml_eval_hessian(um, ud, th)
         nll_o, g_o, _, _ = om.nll(x64, th, order=1)
         h_o = oracle_hessian(om, x64, th)
-        scale = np.sqrt(np.outer(np.diag(h_o), np.diag(h_o)))
+        scale = np.sqrt(np.outer(np.abs(np.diag(h_o)), np.abs(np.diag(h_o))))  # H need not be positive here
         err = np.max(np.abs(h_g - h_o) / scale)
         say(f"  H err {err:.2e}  nll rel {abs(nll_g - nll_o) / abs(nll_o):.2e}")
         assert err <= TOL_H[precision]
@@ -56,6 +57,38 @@ def test_hessian_matches_oracle(name, mk, n, precision):
         # the eval kernel and the Hessian pass agree on NLL and gradient
         nll_e, g_e = uml.uml_eval_nll_grad(um, ud, th)
         assert abs(nll_e - nll_g) <= (1e-12 if precision == "fp64" else 2e-6) * abs(nll_o)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ncomp", [3, 4])
+def test_hessian_of_three_and_four_components(ncomp, precision):
+    """Mixtures of three and four components (nested sums): five and six
+    matrix products per Hessian tile, so two of its waves take a second one.
+    The events are not drawn from the model, so H need not be positive: the
+    scale of an entry is sqrt(|H_aa H_bb|).  FP64 also checks the gradient;
+    the mixed run checks H and the NLL."""
+    desc = mix_desc(ncomp)
+    dtype = np.float32 if precision == "mixed" else np.float64
+    n = 20011
+    x = rng_events(desc, n, 300 + n, dtype)
+    x64 = x.astype(np.float64)
+    om = oracle.Model(desc)
+    um = uml.Model(desc, precision)
+    ud = uml.Data(um, x)
+    say(f"case hessian of {ncomp} components precision={precision}")
+    th = om.theta0
+    nll_g, g_g, h_g = uml.uml_eval_hessian(um, ud, th)
+    nll_o, g_o, _, _ = om.nll(x64, th, order=1)
+    h_o = oracle_hessian(om, x64, th)
+    scale = np.sqrt(np.outer(np.abs(np.diag(h_o)), np.abs(np.diag(h_o))))
+    err = np.max(np.abs(h_g - h_o) / scale)
+    say(f"  H err {err:.2e}  nll rel {abs(nll_g - nll_o) / abs(nll_o):.2e}")
+    assert err <= TOL_H[precision]
+    assert abs(nll_g - nll_o) <= (1e-12 if precision == "fp64" else 1e-6) * abs(nll_o)
+    if precision == "fp64":
+        assert np.max(np.abs(g_g - g_o[om.free]) / np.maximum(np.abs(g_o[om.free]), 1.0)) <= 1e-10
+        nll_e, g_e = uml.uml_eval_nll_grad(um, ud, th)
+        assert abs(nll_e - nll_g) <= 1e-12 * abs(nll_o)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -74,7 +107,7 @@ def test_weighted_hessian_and_w2(precision):
     say(f"case weighted hessian precision={precision}")
     nll_g, g_g, h_g, w2_g = uml.uml_eval_hessian(um, ud, th, want_w2=True)
     h_o = oracle_hessian(om, x64, th, w64)
-    scale = np.sqrt(np.outer(np.diag(h_o), np.diag(h_o)))
+    scale = np.sqrt(np.outer(np.abs(np.diag(h_o)), np.abs(np.diag(h_o))))  # H need not be positive here
     assert np.max(np.abs(h_g - h_o) / scale) <= TOL_H[precision]
     # W2 = sum w^2 s s^T from the oracle's per-event scores
     f = om.free
