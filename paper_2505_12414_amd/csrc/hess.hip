@@ -102,7 +102,10 @@ __device__ __forceinline__ T ld(const void* col, int64_t i) {
   return static_cast<const T*>(col)[i];
 }
 
-// Evaluates one event and writes its staged row.
+// Evaluates one event and writes its staged row.  A parameter belongs to at
+// most one unit of a component (the Hessian plan refuses models where it does
+// not), so each entry of l_c is written once after the zeroing: plain stores,
+// no read-modify-write chains through LDS.
 template <class T>
 __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& cb,
                            const double* hc, const HessPlan& H, int64_t i, T* row) {
@@ -120,7 +123,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
     T v = T(1);
     for (int k = 0; k < C.nfrac; ++k) {
       const int fp = P.free_pos[C.frac_par[k]];
-      if (fp >= 0) l[fp] += T(cb.e[C.frac_ec[k]]);
+      if (fp >= 0) l[fp] = T(cb.e[C.frac_ec[k]]);
     }
     for (int j = 0; j < C.nfac; ++j) {
       const int fi = C.fac[j];
@@ -136,8 +139,8 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           const T lm = fma(d, T(ec[0]), T(ec[1]));
           const T ls = fma(d * d, T(ec[2]), T(ec[3]));
           const int pm = P.free_pos[F.par[0]], ps = P.free_pos[F.par[1]];
-          if (pm >= 0) l[pm] += lm;
-          if (ps >= 0) l[ps] += ls;
+          if (pm >= 0) l[pm] = lm;
+          if (ps >= 0) l[ps] = ls;
           const T is2 = T(ec[0]), is3 = T(ec[2]);
           qf[0] = lm * lm - is2 - T(hc[4 * fi + 0]);
           qf[1] = lm * ls - T(2) * d * is3 - T(hc[4 * fi + 1]);
@@ -149,7 +152,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           e = fma(x, T(kc[0]), e);
           const T lx = x + T(ec[1]);
           const int p = P.free_pos[F.par[0]];
-          if (p >= 0) l[p] += lx;
+          if (p >= 0) l[p] = lx;
           qf[0] = lx * lx + T(hc[4 * fi + 0]);
           break;
         }
@@ -167,7 +170,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           const T iv = T(1) / val;
           for (int jj = 0; jj < k; ++jj) {
             const int p = P.free_pos[F.par[jj]];
-            if (p >= 0) l[p] += fma(T(ec[jj]) * tj[jj + 1], iv, T(ec[k + jj]));
+            if (p >= 0) l[p] = fma(T(ec[jj]) * tj[jj + 1], iv, T(ec[k + jj]));
           }
           int t = 0;
           for (int a = 0; a < k; ++a)
@@ -200,7 +203,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           const T iv = T(1) / val;
           for (int kk = 0; kk < 8; ++kk) {
             const int p = P.free_pos[F.par[kk]];
-            if (p >= 0) l[p] += T(ec[kk]) * m[kk] * iv;
+            if (p >= 0) l[p] = T(ec[kk]) * m[kk] * iv;
           }
           break;
         }
@@ -219,10 +222,25 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
   const T inv = T(1) / sum;
   row[1] = Emax + k_log2(sum);
   for (int c = 0; c < nc; ++c) r[c] = Sp[c] * inv;
-  for (int a = 0; a < nf; ++a) {
-    T sa = T(0);
-    for (int c = 0; c < nc; ++c) sa = fma(r[c], lv[c * nf + a], sa);
-    s[a] = sa;
+  // s = sum_c r_c l_c, four parameters per step: every load of a step is
+  // issued before its stores (s and l_c are disjoint parts of the row)
+  const T* __restrict__ lr = lv;
+  T* __restrict__ sw = s;
+  for (int a0 = 0; a0 < nf; a0 += 4) {
+    T sa[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int c = 0; c < kMaxComp; ++c) {
+      if (c < nc) {
+        T lv4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lv4[u] = a0 + u < nf ? lr[c * nf + a0 + u] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sa[u] = fma(r[c], lv4[u], sa[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (a0 + u < nf) sw[a0 + u] = sa[u];
   }
 }
 
