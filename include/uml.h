@@ -144,8 +144,16 @@ int uml_model_describe(const uml_model* m, char* buf, int32_t len);
  * for UML_FP64).  Every value must lie in its dimension's [lo, hi] after that
  * conversion and every weight must be finite, else UML_E_EVENT_DOMAIN.
  * flags: UML_DATA_DEVICE_SRC -- cols and w are device pointers.
- * The copy runs on stream and is complete when the call returns. */
+ *        UML_DATA_BORROW (with UML_DATA_DEVICE_SRC) -- no copy: the dataset
+ *        reads the caller's device columns (and weights) in place.  dtype must
+ *        be the model's storage type (UML_F32 for UML_MIXED, UML_F64 for
+ *        UML_FP64), every pointer 16-byte aligned, and the model must not store
+ *        precomputed terms (UML_E_INVALID / UML_E_UNSUPPORTED otherwise).  The
+ *        values are checked on the device as above.  The caller keeps the
+ *        buffers alive and unchanged until uml_data_destroy.
+ * The copy (or check) runs on stream and is complete when the call returns. */
 #define UML_DATA_DEVICE_SRC 1
+#define UML_DATA_BORROW 2
 int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int32_t dtype,
                     const void* w, int32_t flags, void* stream, uml_data** out);
 void uml_data_destroy(uml_data* d);

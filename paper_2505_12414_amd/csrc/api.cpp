@@ -3,12 +3,14 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "host.h"
+#include "scatter.h"
 
 namespace uml {
 
@@ -241,6 +243,68 @@ static int data_alloc(const uml_model* m, int64_t n, bool weighted, const DataLa
   return UML_OK;
 }
 
+// UML_DATA_BORROW: the dataset reads the caller's device columns in place;
+// only the work area is allocated.  The values are checked on the device.
+static int data_borrow(const uml_model* m, int64_t n, const void* const* cols, int32_t dtype, const void* w,
+                       int32_t flags, hipStream_t s, uml_data** out) {
+  const char* fn = "uml_data_create";
+  const Plan& P = m->plan;
+  if (!(flags & UML_DATA_DEVICE_SRC))
+    return set_error(UML_E_INVALID, std::string(fn) + ": UML_DATA_BORROW needs UML_DATA_DEVICE_SRC");
+  if (dtype != (P.precision == UML_MIXED ? UML_F32 : UML_F64))
+    return set_error(UML_E_INVALID, std::string(fn) + ": a borrowed column must have the model's storage type");
+  if (P.pre_fac >= 0)
+    return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": a model with precomputed terms cannot borrow columns");
+  if (n < 0) return set_error(UML_E_INVALID, std::string(fn) + ": negative event count");
+  if (n > 0 && !cols) return set_error(UML_E_INVALID, std::string(fn) + ": cols is NULL");
+  for (int ud = 0; n > 0 && ud < P.ndim; ++ud)
+    if (!cols[ud] || reinterpret_cast<uintptr_t>(cols[ud]) % 16)
+      return set_error(UML_E_INVALID, std::string(fn) + ": a borrowed column must be 16-byte aligned");
+  if (w && reinterpret_cast<uintptr_t>(w) % 16)
+    return set_error(UML_E_INVALID, std::string(fn) + ": borrowed weights must be 16-byte aligned");
+  DataLayout L = data_layout(P, n, w != nullptr);
+  L.bytes_events = 0;  // no event storage of its own
+  uml_data* d = nullptr;
+  int rc = data_alloc(m, n, w != nullptr, L, &d, fn);
+  if (rc != UML_OK) return rc;
+  CheckArgs a{};
+  for (int kd = 0; kd < P.ndim; ++kd) {
+    d->job.col[kd] = cols[P.user_of_dim[kd]];
+    a.col[kd] = cols[P.user_of_dim[kd]];
+    a.lo[kd] = P.lo[kd];
+    a.hi[kd] = P.hi[kd];
+  }
+  d->job.w = w;
+  a.w = w;
+  a.ndim = P.ndim;
+  a.fp64 = P.precision == UML_FP64 ? 1 : 0;
+  a.n = n;
+  // the output slot doubles as the violation counter until the work area is
+  // initialised
+  a.bad = reinterpret_cast<unsigned int*>(d->d_out);
+  unsigned int* h_bad = reinterpret_cast<unsigned int*>(d->h_stage);
+  hipError_t e = hipMemsetAsync(a.bad, 0, sizeof(unsigned int), s);
+  if (e == hipSuccess) {
+    launch_check_events(a, s);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h_bad, a.bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = data_init_work(d, L, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    uml_data_destroy(d);
+    return set_error(UML_E_HIP, std::string(fn) + ": " + hipGetErrorString(e));
+  }
+  if (*h_bad) {
+    const unsigned bad = *h_bad;
+    uml_data_destroy(d);
+    return set_error(UML_E_EVENT_DOMAIN, std::string(fn) + ": " + std::to_string(bad) +
+                                             " borrowed values outside their range or not finite");
+  }
+  *out = d;
+  return UML_OK;
+}
+
 }  // namespace uml
 
 using namespace uml;
@@ -345,6 +409,7 @@ int uml_data_create(const uml_model* m, int64_t n, const void* const* cols, int3
   if (n > 0 && cols)
     for (int ud = 0; ud < P.ndim; ++ud)
       if (!cols[ud]) return set_error(UML_E_INVALID, "uml_data_create: column pointer is NULL");
+  if (flags & UML_DATA_BORROW) return data_borrow(m, n, cols, dtype, w, flags, s, out);
   // device sources are copied back to the host first
   std::vector<char> hsrc;
   std::vector<const void*> src(P.ndim, nullptr);

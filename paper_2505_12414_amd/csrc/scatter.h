@@ -1,4 +1,5 @@
-// Packed host<->device transfers for the serving loop: many small pieces for
+// Packed host<->device transfers for the serving loop (and the device-side
+// domain check of borrowed event columns): many small pieces for
 // many destinations travel in one copy and are placed (or collected) by one
 // kernel, instead of one copy each.  Every copy is a separate stream
 // operation with a fixed cost of its own, which dominated admitting and
@@ -8,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "uml.h"
 
 namespace uml {
 
@@ -24,5 +27,18 @@ struct PackRec {
 void launch_scatter(const PackRec* d_recs, int n, const void* d_staging, hipStream_t s);
 // pieces -> staging; one workgroup per record
 void launch_gather(const PackRec* d_recs, int n, void* d_staging, hipStream_t s);
+
+// The domain check of borrowed event columns: every value of kernel dimension
+// d in [lo[d], hi[d]] and every weight finite; bad counts the violations.
+struct CheckArgs {
+  const void* col[UML_MAX_DIMS];
+  const void* w;
+  int ndim;
+  int fp64;
+  int64_t n;
+  double lo[UML_MAX_DIMS], hi[UML_MAX_DIMS];
+  unsigned int* bad;
+};
+void launch_check_events(const CheckArgs& a, hipStream_t s);
 
 }  // namespace uml

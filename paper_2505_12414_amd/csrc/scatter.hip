@@ -28,7 +28,33 @@ __global__ __launch_bounds__(256) void gather_kernel(const PackRec* __restrict__
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void check_events_kernel(const CheckArgs a) {
+  unsigned int bad = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * 256) {
+    for (int d = 0; d < a.ndim; ++d) {
+      const double v = double(static_cast<const T*>(a.col[d])[i]);
+      if (!(v >= a.lo[d] && v <= a.hi[d])) ++bad;  // also catches NaN
+    }
+    if (a.w) {
+      const double v = double(static_cast<const T*>(a.w)[i]);
+      if (!isfinite(v)) ++bad;
+    }
+  }
+  if (bad) atomicAdd(a.bad, bad);
+}
+
 }  // namespace
+
+void launch_check_events(const CheckArgs& a, hipStream_t s) {
+  if (a.n <= 0) return;
+  const int64_t want = (a.n + 255) / 256;
+  const unsigned blocks = unsigned(want < 4096 ? want : 4096);
+  if (a.fp64)
+    hipLaunchKernelGGL(check_events_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(check_events_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+}
 
 void launch_scatter(const PackRec* d_recs, int n, const void* d_staging, hipStream_t s) {
   if (n <= 0) return;

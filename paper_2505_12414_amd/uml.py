@@ -37,6 +37,7 @@ UML_E_GENERATION = -11
 UML_FP64, UML_MIXED = 0, 1
 UML_F32, UML_F64 = 0, 1
 UML_DATA_DEVICE_SRC = 1
+UML_DATA_BORROW = 2
 MAX_PARAMS = 32
 
 KINDS = {"gauss": 1, "exp": 2, "cheb": 3, "pwave": 4, "prod": 5, "sum": 6}
@@ -251,12 +252,17 @@ class Model:
 
 class Data:
     """uml_data_create / uml_data_destroy.  events: array (n_dims, n) of
-    float32 or float64 (host numpy, or a torch CUDA tensor for device upload)."""
+    float32 or float64 (host numpy, or a torch CUDA tensor for device upload).
+    borrow=True (CUDA tensors only, UML_DATA_BORROW): the dataset reads the
+    tensor's rows in place; they must have the model's storage type and start
+    on 16-byte boundaries (n a multiple of 4 for FP32 rows, of 2 for FP64), and
+    this object keeps the tensors alive."""
 
-    def __init__(self, model, events, weights=None, stream=None):
+    def __init__(self, model, events, weights=None, stream=None, borrow=False):
         self.model = model
         flags = 0
         keep = []
+        self._keep = None
         if hasattr(events, "is_cuda") and events.is_cuda:
             import torch
             ev = events.contiguous()
@@ -274,7 +280,12 @@ class Data:
                 wptr = wt.data_ptr()
             flags |= UML_DATA_DEVICE_SRC
             keep.append(ev)
+            if borrow:
+                flags |= UML_DATA_BORROW
+                self._keep = keep
         else:
+            if borrow:
+                raise ValueError("borrow=True needs CUDA tensors")
             ev = np.asarray(events)
             if ev.ndim == 1:
                 ev = ev.reshape(1, -1)
