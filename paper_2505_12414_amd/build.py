@@ -24,13 +24,17 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 # registers, which would otherwise add to every event kernel's register count
 # and cost it a wave per SIMD.
 HIP_FLAGS = ["-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
+# Per source: the event kernels take their point, cached constants,
+# parameter count, tile map and job array as five leading arguments preloaded into
+# scalar registers.
+SOURCE_FLAGS = {"eval.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=5"]}
 SOURCES = ["eval.hip", "hess.hip", "gen.hip", "scatter.hip", "model.cpp", "api.cpp", "fit.cpp", "server.cpp"]
 
 
 def _compile(src, verbose):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJ, src + ".o")
-    lang = ["-x", "hip"] + HIP_FLAGS if src.endswith(".hip") else []
+    lang = ["-x", "hip"] + HIP_FLAGS + SOURCE_FLAGS.get(src, []) if src.endswith(".hip") else []
     cmd = [HIPCC] + FLAGS + lang + ["-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

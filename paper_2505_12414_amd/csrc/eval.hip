@@ -789,25 +789,42 @@ __host__ __device__ constexpr int eval_min_waves() {
   return (P::VW == 4 && !S::pre) ? 4 : 1;
 }
 
+// A launch without a tile map evaluates job j0 at the point theta0, with the
+// job's cached constant block cst0 and parameter count npar0.  These lead the
+// argument list, followed by the tile map; the hardware preloads the four into
+// scalar registers (the library is built that way), so without a tile map the
+// loads of the cache check go out without waiting for the rest of the
+// arguments.  With a tile map each workgroup takes its job's own instead.
 template <class S, class P>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min_waves<S, P>()))) void eval_kernel(const Job j0, const Job* __restrict__ jobs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min_waves<S, P>()))) void eval_kernel(const double* __restrict__ theta0,
+                                                      const ConstBlock* __restrict__ cst0, int npar0,
                                                       const int2* __restrict__ tmap,
-                                                      const double* __restrict__ theta_override,
-                                                      double* __restrict__ out_override) {
+                                                      const Job* __restrict__ jobs,
+                                                      double* __restrict__ out_override, const Job j0) {
   using T = typename P::T;
   constexpr int K = S::K;
+  const int tid = threadIdx.x, lane = tid & 63;
   int jid = 0, tile = blockIdx.x;
+  const double* __restrict__ th = theta0;
+  const ConstBlock* __restrict__ gc = cst0;
+  int npar = npar0;
   if (tmap) {
     const int2 t = tmap[blockIdx.x];
     jid = t.x;
     tile = t.y;
     if (jid < 0) return;
+    th = jobs[jid].theta;
+    gc = jobs[jid].cst;
+    npar = jobs[jid].npar;
   }
+  // the cache check's loads, issued before the fit's done flag is known and
+  // unconditionally (lanes past the parameter count re-read parameter 0, and
+  // every model has at least one), so nothing waits for them until the check
+  const int pl = lane < npar ? lane : 0;
+  const double th_l = th[pl], gc_l = gc->theta[pl];
   const Job J = tmap ? jobs[jid] : j0;
   if (J.fit && J.fit->done) return;  // a finished fit: its tiles do nothing
   __shared__ __align__(16) ConstBlock s_cb;
-  const double* __restrict__ th = (theta_override && !tmap) ? theta_override : J.theta;
-  const int tid = threadIdx.x, lane = tid & 63;
 
   // Parameter-only constants.  The job keeps the block of the last point it
   // evaluated: when theta matches it bit for bit its constants are used
@@ -835,19 +852,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   __shared__ double red2[K * (PARTS > 16 ? PARTS : 16)];
   __shared__ int s_flag;
 
-  const ConstBlock* __restrict__ gc = J.cst;
   T c[S::ncst];
 #pragma unroll
   for (int i = 0; i < S::ncst; ++i) c[i] = P::consts(gc)[i];
   T xref[S::ndim];  // only shifted dimensions (all below UML_MAX_DIMS) have one
 #pragma unroll
   for (int d = 0; d < S::ndim; ++d) xref[d] = ((S::shift_mask >> d) & 1u) ? P::xrefs(gc)[d] : T(0);
-  bool eq = true;
-  if (lane < J.npar)
-    eq = __double_as_longlong(th[lane]) == __double_as_longlong(gc->theta[lane]);
+  const bool eq = lane >= npar || __double_as_longlong(th_l) == __double_as_longlong(gc_l);
   const bool hit = __all(eq) && gc->valid;  // the same in every wave
   if (!hit) {
-    miss_prologue(J.plan, th, J.npar, red, &s_cb);
+    miss_prologue(J.plan, th, npar, red, &s_cb);
 #pragma unroll
     for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
 #pragma unroll
@@ -955,12 +969,13 @@ top_level:
 
 template <class S>
 void launch_eval(const LaunchArgs& a) {
+  const double* th0 = a.theta ? a.theta : a.job0.theta;
   if (a.precision == UML_MIXED)
-    hipLaunchKernelGGL((eval_kernel<S, PrecMixed>), dim3(a.grid), dim3(kBlock), 0, a.stream,
-                       a.job0, a.jobs, a.tmap, a.theta, a.out);
+    hipLaunchKernelGGL((eval_kernel<S, PrecMixed>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
+                       a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
   else
-    hipLaunchKernelGGL((eval_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream,
-                       a.job0, a.jobs, a.tmap, a.theta, a.out);
+    hipLaunchKernelGGL((eval_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
+                       a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
 }
 
 template <class S>

@@ -216,6 +216,7 @@ static __device__ __forceinline__ bool factor_constants(const FactorPlan& F, con
 }
 
 static_assert(kMaxFac <= 32 && kMaxComp * 8 <= 32, "prologue tasks: factors on lanes 0-31, fractions on 32-63");
+static_assert((kMaxFac & (kMaxFac - 1)) == 0, "factor indices are masked with kMaxFac - 1");
 
 // The waves of the two stages, chosen so that the slow pieces run side by
 // side on different SIMDs: stage 1 puts the Gaussian halves on waves 0 and 1
@@ -296,27 +297,28 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
   const bool wave_bad = __ballot(ok ? 0 : 1) != 0;
   if (lane == 0 && w < 16) s_bad[w] = wave_bad ? 1 : 0;
   __syncthreads();
-  // stage 3 (unrolled to the maximum counts, so the reads go out together)
+  // stage 3 (unrolled to the maximum counts, with every read unconditional and
+  // the unused entries replaced by zero, so the reads go out together)
   if (tid < P.ncomp) {
     const CompPlan& C = P.comp[tid];
+    const int nfrac = C.nfrac, nfac = C.nfac;
+    double v[8 + kMaxFacPerComp];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = s_fl2[tid * 8 + k];
+#pragma unroll
+    for (int j = 0; j < kMaxFacPerComp; ++j) v[8 + j] = s_ln2[C.fac[j] & (kMaxFac - 1)];
     double lk2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double v = s_fl2[tid * 8 + k];
-      if (k < C.nfrac) lk2 += v;
-    }
+    for (int k = 0; k < 8; ++k) lk2 += k < nfrac ? v[k] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kMaxFacPerComp; ++j) {
-      const int f = j < C.nfac ? C.fac[j] : 0;
-      const double v = s_ln2[f];
-      if (j < C.nfac) lk2 += v;
-    }
+    for (int j = 0; j < kMaxFacPerComp; ++j) lk2 += j < nfac ? v[8 + j] : 0.0;
     cb->d[C.cst_lk2] = lk2;
     cb->f[C.cst_lk2] = float(lk2);
   }
   if (tid == 0) {
     int bad = 0;
-    for (int i = 0; i < nw && i < 16; ++i) bad |= s_bad[i];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) bad |= i < nw ? s_bad[i] : 0;
     cb->domain_ok = bad ? 0 : 1;
     cb->valid = 1;
   }
