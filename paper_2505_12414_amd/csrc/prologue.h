@@ -54,25 +54,26 @@ static __device__ __forceinline__ double d_phi_diff(double za, double zb) {
 static constexpr double kLog2e = 1.4426950408889634074;
 static constexpr double kSqrt2Pi = 2.5066282746310005024;
 
-// Stage 1 of the prologue: the transcendental functions of the Gaussian and
-// exponential factors, in two halves that run on different waves.  tr:
-//   Gaussian     half 0: tr[0] = erfc(u), tr[2] = exp(-za^2/2)
-//                half 1: tr[1] = erfc(v), tr[3] = exp(-zb^2/2)
-//   exponential  half 0: tr[0] = expm1(lambda L)
-//                half 1: tr[1] = expm1(-lambda L) (unused near lambda L = 0)
+// Stage 1 of the prologue: one transcendental function of a Gaussian or
+// exponential factor per task; piece p of a factor runs on wave
+// stage1_wave(kind, p), its half h (the two ends of the range) on lanes
+// f and 16 + f of that wave, so both halves take one pass of the same code.
+//   Gaussian     piece 0: tr[h] = erfc(u), erfc(v)
+//                piece 1: tr[2 + h] = exp(-za^2/2), exp(-zb^2/2)
+//   exponential  piece 0: tr[h] = expm1(lambda L), expm1(-lambda L) (the latter
+//                unused near lambda L = 0)
 static __device__ __forceinline__ void factor_stage1(const FactorPlan& F, const double* __restrict__ th,
-                                                     int half, double* tr) {
+                                                     int piece, int half, double* tr) {
   if (F.kind == FK_GAUSS) {
     const double mu = th[F.par[0]], sg = th[F.par[1]];
     const double za = (F.lo[0] - mu) / sg, zb = (F.hi[0] - mu) / sg;
-    double u, v;
-    phi_diff_args(za, zb, u, v);
-    if (half == 0) {
-      tr[0] = p_erfc(u);
-      tr[2] = p_exp(-0.5 * za * za);
+    if (piece == 0) {
+      double u, v;
+      phi_diff_args(za, zb, u, v);
+      tr[half] = p_erfc(half ? v : u);
     } else {
-      tr[1] = p_erfc(v);
-      tr[3] = p_exp(-0.5 * zb * zb);
+      const double z = half ? zb : za;
+      tr[2 + half] = p_exp(-0.5 * z * z);
     }
   } else if (F.kind == FK_EXP) {
     const double lam = th[F.par[0]], z = lam * (F.hi[0] - F.lo[0]);
@@ -215,15 +216,16 @@ static __device__ __forceinline__ bool factor_constants(const FactorPlan& F, con
   return false;
 }
 
-static_assert(kMaxFac <= 32 && kMaxComp * 8 <= 32, "prologue tasks: factors on lanes 0-31, fractions on 32-63");
+static_assert(kMaxFac <= 16 && kMaxComp * 8 <= 32, "prologue tasks: factors on lanes 0-31, fractions on 32-63");
 static_assert((kMaxFac & (kMaxFac - 1)) == 0, "factor indices are masked with kMaxFac - 1");
 
 // The waves of the two stages, chosen so that the slow pieces run side by
-// side on different SIMDs: stage 1 puts the Gaussian halves on waves 0 and 1
-// and the exponential halves (and the fractions) on waves 2 and 3; stage 2
-// gives each factor kind a wave of its own.
-static __device__ __forceinline__ int stage1_wave(int kind, int half, int nwaves) {
-  return ((kind == FK_GAUSS ? 0 : 2) + half) % nwaves;
+// side on different SIMDs: stage 1 puts the Gaussians' erfc on wave 0, their
+// exp on wave 1, the exponentials' expm1 on wave 2 and the fractions on wave 3;
+// stage 2 gives each factor kind a wave of its own.
+static constexpr int kFracWave = 3;
+static __device__ __forceinline__ int stage1_wave(int kind, int piece, int nwaves) {
+  return (kind == FK_GAUSS ? piece : 2) % nwaves;
 }
 static __device__ __forceinline__ int prologue_wave(int kind, int nwaves) {
   return (kind >= FK_GAUSS && kind <= FK_PWAVE) ? (kind - FK_GAUSS) % nwaves : 0;
@@ -246,9 +248,10 @@ static __device__ __forceinline__ auto lds(T* p) {
 // a multiple of 64, at most 1024 (it synchronises the workgroup; the caller
 // synchronises again before other threads read cb).  P, th (all npar
 // parameters) and cb sit in LDS (store_const_block copies cb out).
-//   stage 1  lane f of the waves of stage1_wave: the transcendental halves of
-//            factor f; lane 32 + 8c + k of wave 2: fraction entry k of
-//            component c (log2 and d ln F_c / d f);
+//   stage 1  lanes f and 16 + f of the waves of stage1_wave: the
+//            transcendental functions of factor f; lane 32 + 8c + k of
+//            wave kFracWave: fraction entry k of component c (log2 and
+//            d ln F_c / d f);
 //   stage 2  lane f of the wave of its kind: factor f's constants;
 //   stage 3  lane c of wave 0: component c's log2 prefactor, summed in a
 //            fixed order (its fractions, then its factors), so the result
@@ -266,13 +269,14 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
   const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
   bool ok = true;
   // stage 1
-  if (lane < P.nfac) {
-    const FactorPlan& F = P.fac[lane];
+  if (lane < 32 && (lane & 15) < P.nfac) {
+    const int f = lane & 15, half = lane >> 4;
+    const FactorPlan& F = P.fac[f];
     if (F.kind == FK_GAUSS || F.kind == FK_EXP)
-      for (int h = 0; h < 2; ++h)
-        if (stage1_wave(F.kind, h, nw) == w) factor_stage1(F, th, h, s_tr[lane]);
+      for (int piece = 0; piece < (F.kind == FK_GAUSS ? 2 : 1); ++piece)
+        if (stage1_wave(F.kind, piece, nw) == w) factor_stage1(F, th, piece, half, s_tr[f]);
   }
-  if (lane >= 32 && w == 2 % nw) {
+  if (lane >= 32 && w == kFracWave % nw) {
     const int c = (lane - 32) >> 3, k = (lane - 32) & 7;
     if (c < P.ncomp && k < P.comp[c].nfrac) {
       const CompPlan& C = P.comp[c];
