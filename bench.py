@@ -46,7 +46,8 @@ FLOP_PER_EVENT_4D = 137
 # Sources of the event kernels: HBM traffic measured with hardware counters
 # (profiles/) is reported only while these are unchanged.
 KERNEL_SOURCES = ["paper_2505_12414_amd/csrc/eval.hip", "paper_2505_12414_amd/csrc/prologue.h",
-                  "paper_2505_12414_amd/csrc/devmath.h", "paper_2505_12414_amd/csrc/uml_internal.h"]
+                  "paper_2505_12414_amd/csrc/devmath.h", "paper_2505_12414_amd/csrc/uml_internal.h",
+                  "paper_2505_12414_amd/build.py"]  # the build flags shape the kernel too
 COPY_MB = 512
 
 SEED_DATA = 20250512
@@ -205,6 +206,37 @@ def headline(args, torch, uml, G, W):
                                 "fixed_us": round(us1 - n * per_event_s * 1e6, 3),
                                 "achieved": round(tf, 3), "frac": round(tf / peak, 4)}
         del data2, x2
+    if args.rotate > 1:
+        # the same evaluations over `rotate` distinct datasets of the same
+        # shape, one per launch in turn: with a working set beyond the 256 MB
+        # last-level cache each launch reads its events from HBM ("cold");
+        # the main figure above is the fit loop's own, one dataset ("hot")
+        gen = G.gen_angmass4d if args.model == "angmass4d" else G.gen_mass1d
+        ds = [data] + [uml.Data(model, gen(n, seed=SEED_DATA + 100 + r, dtype=dtype))
+                       for r in range(args.rotate - 1)]
+        steps_c = max(args.rotate * 4, (args.steps // args.rotate) * args.rotate)
+        with torch.cuda.stream(stream):
+            for i in range(args.rotate * 2):
+                uml.uml_eval_nll_grad_dev(model, ds[i % args.rotate], points[i % len(points)], out,
+                                          stream=stream)
+            eca, ecb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            eca.record(stream)
+            for i in range(steps_c):
+                uml.uml_eval_nll_grad_dev(model, ds[i % args.rotate], points[i % len(points)], out,
+                                          stream=stream)
+            ecb.record(stream)
+        torch.cuda.synchronize()
+        us_c = eca.elapsed_time(ecb) / steps_c * 1e3
+        cold = {"datasets": args.rotate, "working_set_mb": round(args.rotate * n * esize * len(desc["dims"]) / 1e6, 1),
+                "steps": steps_c, "us_per_step": round(us_c, 3)}
+        if roofline["bound"] == "hbm":
+            ach = roofline["bytes_per_event"] * n / (us_c * 1e-6) / 1e9
+        else:
+            ach = FLOP_PER_EVENT_4D * n / (us_c * 1e-6) / 1e12
+        cold["achieved"] = round(ach, 3)
+        cold["frac"] = round(ach / roofline["peak"], 4)
+        roofline["cold"] = cold
+        del ds
     with torch.cuda.stream(stream):  # the reported NLL: at the generating point
         uml.uml_eval_nll_grad_dev(model, data, theta, out, stream=stream)
     torch.cuda.synchronize()
@@ -485,6 +517,9 @@ def main():
                     help="4-D model with the P-wave's event-only terms stored per event")
     ap.add_argument("--marginal-events", type=int, default=4_000_000,
                     help="second dataset size for the per-event (marginal) rate; 0: skip")
+    ap.add_argument("--rotate", type=int, default=1,
+                    help="also time the evaluations over this many distinct datasets in turn "
+                         "(a working set beyond the last-level cache); 1: skip")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this implementation runs on one GPU (asked for {args.gpus}); "
