@@ -268,6 +268,24 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
   const int tid = threadIdx.x;
   const int nw = blockDim.x >> 6, w = tid >> 6, lane = tid & 63;
   bool ok = true;
+  // Plan entries of stages 2 and 3, and the point's copy, read before stage 1
+  // so that their LDS round trips overlap it: the factor kind of lane f, and
+  // the fraction count, factor count, factors and output slot of component c
+  // (lane c of wave 0).
+  const int nfac = P.nfac, npar = P.npar, ncomp = P.ncomp;
+  const int kind2 = lane < nfac ? P.fac[lane].kind : -1;
+  const double th_copy = (w == nw - 1 && lane >= 32 && lane - 32 < npar) ? th[lane - 32] : 0.0;
+  int c_nfrac = 0, c_nfac = 0, c_lk2 = 0, c_fac[kMaxFacPerComp];
+#pragma unroll
+  for (int j = 0; j < kMaxFacPerComp; ++j) c_fac[j] = 0;
+  if (tid < ncomp) {
+    const CompPlan& C = P.comp[tid];
+    c_nfrac = C.nfrac;
+    c_nfac = C.nfac;
+    c_lk2 = C.cst_lk2;
+#pragma unroll
+    for (int j = 0; j < kMaxFacPerComp; ++j) c_fac[j] = C.fac[j] & (kMaxFac - 1);
+  }
   // stage 1
   if (lane < 32 && (lane & 15) < P.nfac) {
     const int f = lane & 15, half = lane >> 4;
@@ -292,32 +310,30 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
   }
   __syncthreads();
   // stage 2
-  if (lane < P.nfac && prologue_wave(P.fac[lane].kind, nw) == w) {
+  if (kind2 >= 0 && prologue_wave(kind2, nw) == w) {
     const FactorPlan& F = P.fac[lane];
     const KOut ko{cb->d + F.cst, cb->f + F.cst};
     ok = factor_constants(F, th, s_tr[lane], ko, cb->e + F.ecst, &s_ln2[lane]) && ok;
   }
-  if (w == nw - 1 && lane >= 32 && lane - 32 < P.npar) cb->theta[lane - 32] = th[lane - 32];
+  if (w == nw - 1 && lane >= 32 && lane - 32 < npar) cb->theta[lane - 32] = th_copy;
   const bool wave_bad = __ballot(ok ? 0 : 1) != 0;
   if (lane == 0 && w < 16) s_bad[w] = wave_bad ? 1 : 0;
   __syncthreads();
   // stage 3 (unrolled to the maximum counts, with every read unconditional and
   // the unused entries replaced by zero, so the reads go out together)
-  if (tid < P.ncomp) {
-    const CompPlan& C = P.comp[tid];
-    const int nfrac = C.nfrac, nfac = C.nfac;
+  if (tid < ncomp) {
     double v[8 + kMaxFacPerComp];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] = s_fl2[tid * 8 + k];
 #pragma unroll
-    for (int j = 0; j < kMaxFacPerComp; ++j) v[8 + j] = s_ln2[C.fac[j] & (kMaxFac - 1)];
+    for (int j = 0; j < kMaxFacPerComp; ++j) v[8 + j] = s_ln2[c_fac[j]];
     double lk2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) lk2 += k < nfrac ? v[k] : 0.0;
+    for (int k = 0; k < 8; ++k) lk2 += k < c_nfrac ? v[k] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kMaxFacPerComp; ++j) lk2 += j < nfac ? v[8 + j] : 0.0;
-    cb->d[C.cst_lk2] = lk2;
-    cb->f[C.cst_lk2] = float(lk2);
+    for (int j = 0; j < kMaxFacPerComp; ++j) lk2 += j < c_nfac ? v[8 + j] : 0.0;
+    cb->d[c_lk2] = lk2;
+    cb->f[c_lk2] = float(lk2);
   }
   if (tid == 0) {
     int bad = 0;
