@@ -791,10 +791,11 @@ __host__ __device__ constexpr int eval_min_waves() {
 
 // A launch without a tile map evaluates job j0 at the point theta0, with the
 // job's cached constant block cst0 and parameter count npar0.  These lead the
-// argument list, followed by the tile map; the hardware preloads the four into
-// scalar registers (the library is built that way), so without a tile map the
-// loads of the cache check go out without waiting for the rest of the
-// arguments.  With a tile map each workgroup takes its job's own instead.
+// argument list, followed by the tile map and the job array; the hardware
+// preloads the five into scalar registers (the library is built that way), so
+// without a tile map the loads of the cache check go out without waiting for
+// the rest of the arguments.  With a tile map each workgroup takes its job's
+// own point, block and count from the job array instead.
 template <class S, class P>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min_waves<S, P>()))) void eval_kernel(const double* __restrict__ theta0,
                                                       const ConstBlock* __restrict__ cst0, int npar0,
@@ -828,9 +829,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
 
   // Parameter-only constants.  The job keeps the block of the last point it
   // evaluated: when theta matches it bit for bit its constants are used
-  // (scalar loads, issued together with the comparison); otherwise the first
-  // lane computes them here in FP64 (the prologue: normalisations, combined
-  // prefactors, angular coefficients).
+  // (scalar loads, issued together with the comparison); otherwise the
+  // workgroup computes them here in FP64 (the prologue: normalisations,
+  // combined prefactors, angular coefficients).
   const int64_t tsize = int64_t(J.events_per_thread) * kBlock;
   const int64_t base = int64_t(tile) * tsize;
   const bool full = base + tsize <= J.n;
