@@ -230,13 +230,6 @@ struct uml_server {
   int hmap_cap = 0;
   double* h_hsums = nullptr;
   double* d_hsums = nullptr;
-  // the same for retirement, in flight together with an admission
-  HessJob* h_hjobs_r = nullptr;
-  HessJob* d_hjobs_r = nullptr;
-  int2* h_hmap_r = nullptr;
-  int2* d_hmap_r = nullptr;
-  double* h_hsums_r = nullptr;
-  double* d_hsums_r = nullptr;
   unsigned int* d_genbad = nullptr;  // per slot: events that failed to draw
   unsigned int* h_genbad = nullptr;
   // batched generation: job table and block map (pinned and device)
@@ -310,12 +303,7 @@ bool pack_init(Packer& up, const uml_data& d, const DataLayout& L, const double*
          up.zero(w + L.o_out, L.o_part - L.o_out);
 }
 
-// Admission, device part: places each request of the batch in its slot's
-// arena memory, queues its events (upload or generation), its initialised
-// work area and the Hessian pass at its start point (the start metric), and
-// the copies of the sums back.  admit_finish completes it once the stream has
-// been synchronised.
-int admit_queue(uml_server* S, std::vector<Intake>& in) {
+int admit_batch(uml_server* S, std::vector<Intake>& in) {
   const uml_model* m = S->m;
   const int ns = int(S->slots.size());
   UML_HIP_CHECK(S->up.reset(S->stream));
@@ -389,17 +377,7 @@ int admit_queue(uml_server* S, std::vector<Intake>& in) {
                                S->stream));
   UML_HIP_CHECK(hipMemcpyAsync(S->h_genbad, S->d_genbad, sizeof(unsigned int) * ns, hipMemcpyDeviceToHost,
                                S->stream));
-  return UML_OK;
-}
-
-// Admission, host part (after the stream is synchronised): a request whose
-// events could not be drawn or whose start point has P <= 0 somewhere is
-// answered at once; the others get their fit state (start metric from the
-// Hessian), uploaded packed with their jobs.
-int admit_finish(uml_server* S, std::vector<Intake>& in) {
-  const uml_model* m = S->m;
-  const int nb = int(in.size()), M = hess_sums(m);
-  int rc = UML_OK;
+  UML_HIP_CHECK(hipStreamSynchronize(S->stream));
   for (int j = 0; j < nb; ++j) {
     const int i = in[j].slot;
     Slot& sl = S->slots[i];
@@ -444,12 +422,13 @@ int admit_finish(uml_server* S, std::vector<Intake>& in) {
   return UML_OK;
 }
 
-// Retirement, device part: queues the collection of the finished fit states
-// and the Hessian pass at each final point (read on the device), with its own
-// job tables and sums, so that it can share one synchronisation with an
-// admission.  retire_finish forms the results.
-int retire_queue(uml_server* S, const std::vector<int>& fin) {
+// Retires a batch of finished fits: queues, for each, the copy of its fit
+// state and the Hessian pass at its final point (read on the device), waits
+// once, then forms the results (covariance from the inverse Hessian) and
+// frees the slots.  Newton polishing, when asked for, runs fit by fit.
+int retire_batch(uml_server* S, const std::vector<int>& fin) {
   const uml_model* m = S->m;
+  const Plan& P = m->plan;
   const bool polish = S->opt.fit.polish > 0;
   const int nb = int(fin.size()), M = hess_sums(m);
   // the finished fit states, collected by one kernel and one copy
@@ -466,23 +445,13 @@ int retire_queue(uml_server* S, const std::vector<int>& fin) {
       ds[j] = &S->slots[fin[j]].data;
       th[j] = S->d_fs[fin[j]].theta;
     }
-    int rc = hessian_queue_batch(m, ds.data(), th.data(), nb, S->d_hsums_r, S->h_hjobs_r, S->d_hjobs_r,
-                                 S->h_hmap_r, S->d_hmap_r, S->hmap_cap, S->stream, "server");
+    int rc = hessian_queue_batch(m, ds.data(), th.data(), nb, S->d_hsums, S->h_hjobs, S->d_hjobs,
+                                 S->h_hmap, S->d_hmap, S->hmap_cap, S->stream, "server");
     if (rc != UML_OK) return rc;
-    UML_HIP_CHECK(hipMemcpyAsync(S->h_hsums_r, S->d_hsums_r, sizeof(double) * nb * M, hipMemcpyDeviceToHost,
+    UML_HIP_CHECK(hipMemcpyAsync(S->h_hsums, S->d_hsums, sizeof(double) * nb * M, hipMemcpyDeviceToHost,
                                  S->stream));
   }
-  return UML_OK;
-}
-
-// Retirement, host part (after the stream is synchronised): the results
-// (covariance from the inverse Hessian), then the slots are freed.  Newton
-// polishing, when asked for, runs fit by fit.
-int retire_finish(uml_server* S, const std::vector<int>& fin) {
-  const uml_model* m = S->m;
-  const Plan& P = m->plan;
-  const bool polish = S->opt.fit.polish > 0;
-  const int nb = int(fin.size()), M = hess_sums(m);
+  UML_HIP_CHECK(hipStreamSynchronize(S->stream));
   for (int j = 0; j < nb; ++j)
     std::memcpy(&S->h_slots[fin[j]].fs, S->h_gst + sizeof(FitState) * j, sizeof(FitState));
   for (int j = 0; j < nb; ++j) {
@@ -499,7 +468,7 @@ int retire_finish(uml_server* S, const std::vector<int>& fin) {
       for (int k = 0; k < P.npar; ++k) r.params[k] = F.theta[k];
       r.nll = INFINITY;
     } else if (!polish) {
-      finish_from_sums(m, S->h_hsums_r + size_t(j) * M, F.theta, S->opt.fit, &r, "server");
+      finish_from_sums(m, S->h_hsums + size_t(j) * M, F.theta, S->opt.fit, &r, "server");
     } else {
       std::vector<double> theta(F.theta, F.theta + P.npar);
       int rc = finish_fit(m, &sl.data, theta, S->opt.fit, &r, S->stream, "server");
@@ -550,13 +519,9 @@ void free_server_memory(uml_server* S) {
                   static_cast<void*>(S->h_hjobs), static_cast<void*>(S->h_hmap),
                   static_cast<void*>(S->h_hsums), static_cast<void*>(S->h_genbad),
                   static_cast<void*>(S->h_genjobs), static_cast<void*>(S->h_genmap),
-                  static_cast<void*>(S->up.h), static_cast<void*>(S->h_grecs), static_cast<void*>(S->h_gst),
-                  static_cast<void*>(S->h_hjobs_r), static_cast<void*>(S->h_hmap_r),
-                  static_cast<void*>(S->h_hsums_r)})
+                  static_cast<void*>(S->up.h), static_cast<void*>(S->h_grecs), static_cast<void*>(S->h_gst)})
     if (p) (void)hipHostFree(p);
-  for (void* p : {static_cast<void*>(S->up.d), static_cast<void*>(S->d_grecs), static_cast<void*>(S->d_gst),
-                  static_cast<void*>(S->d_hjobs_r), static_cast<void*>(S->d_hmap_r),
-                  static_cast<void*>(S->d_hsums_r)})
+  for (void* p : {static_cast<void*>(S->up.d), static_cast<void*>(S->d_grecs), static_cast<void*>(S->d_gst)})
     if (p) (void)hipFree(p);
   if (S->stream) (void)hipStreamDestroy(S->stream);
 }
@@ -565,14 +530,14 @@ void worker_main(uml_server* S) {
   (void)hipSetDevice(S->m->device);
   const int ns = int(S->slots.size());
   std::vector<int2> map;
-  std::vector<int> fin;  // fits found finished by the last replay, not yet retired
+  std::vector<int> fin;
   bool dirty = true;
   int bucket = 0;
   while (true) {
     std::vector<Intake> intake;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->stop && S->pending.empty() && S->active == 0 && fin.empty()) break;
+      if (S->stop && S->pending.empty() && S->active == 0) break;
       // admission, in arrival order: a free slot and room in the arena (the
       // memory budget); the arena belongs to this thread
       for (int i = 0; i < ns && !S->pending.empty(); ++i) {
@@ -587,41 +552,23 @@ void worker_main(uml_server* S) {
         intake.push_back({i, off, std::move(S->pending.front())});
         S->pending.pop_front();
       }
-      if (intake.empty() && fin.empty() && S->active == 0) {
+      if (intake.empty() && S->active == 0) {
         S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
         continue;
       }
       S->admitted += int64_t(intake.size());
     }
-    // the retirement of the last replay's finished fits and the admission of
-    // new requests share one synchronisation: both are queued first, then
-    // their host parts run
-    if (!fin.empty() || !intake.empty()) {
+    if (!intake.empty()) {
       const double t0 = now_s();
-      int rc = fin.empty() ? UML_OK : retire_queue(S, fin);
-      const double t1 = now_s();
-      if (rc == UML_OK && !intake.empty()) rc = admit_queue(S, intake);
-      if (rc == UML_OK) {
-        const hipError_t e = hipStreamSynchronize(S->stream);
-        if (e != hipSuccess) rc = set_error(UML_E_HIP, std::string("server: ") + hipGetErrorString(e));
-        S->up.unsynced = false;
-      }
-      const double t2 = now_s();
-      if (rc == UML_OK && !fin.empty()) rc = retire_finish(S, fin);
-      const double t3 = now_s();
-      if (rc == UML_OK && !intake.empty()) rc = admit_finish(S, intake);
-      const double t4 = now_s();
+      int rc = admit_batch(S, intake);
       {
         std::lock_guard<std::mutex> lk(S->mu);
-        // the shared wait counts for the admission when there is one
-        S->t_retire += (t1 - t0) + (t3 - t2) + (intake.empty() ? t2 - t1 : 0.0);
-        S->t_admit += (t4 - t3) + (intake.empty() ? 0.0 : t2 - t1);
+        S->t_admit += now_s() - t0;
       }
       if (rc != UML_OK) {
         fail_worker(S, rc, uml_last_error());
         return;
       }
-      fin.clear();
       dirty = true;
     }
     if (S->active == 0) continue;
@@ -660,14 +607,27 @@ void worker_main(uml_server* S) {
       fail_worker(S, UML_E_HIP, std::string("server iteration: ") + hipGetErrorString(e));
       return;
     }
-    S->up.unsynced = false;
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->iterations += kItersPerReplay;
       S->t_iterate += now_s() - t_it;
     }
+    fin.clear();
     for (int i = 0; i < ns; ++i)
       if (S->slots[i].used && S->h_done[i]) fin.push_back(i);
+    if (!fin.empty()) {
+      const double t0 = now_s();
+      rc = retire_batch(S, fin);
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->t_retire += now_s() - t0;
+      }
+      if (rc != UML_OK) {
+        fail_worker(S, rc, uml_last_error());
+        return;
+      }
+      dirty = true;
+    }
   }
 }
 
@@ -770,19 +730,6 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&S->h_gst), sizeof(FitState) * ns, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_gst), sizeof(FitState) * ns);
-  // retirement's Hessian job tables, tile map and sums (in flight together
-  // with an admission's)
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hjobs_r), sizeof(HessJob) * ns, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_hjobs_r), sizeof(HessJob) * ns);
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hmap_r), sizeof(int2) * size_t(S->hmap_cap),
-                      hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_hmap_r), sizeof(int2) * size_t(S->hmap_cap));
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hsums_r), sizeof(double) * size_t(ns) * M,
-                      hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_hsums_r), sizeof(double) * size_t(ns) * M);
   if (e != hipSuccess) return fail(e, "pinned staging");
   S->arena.init(static_cast<char*>(S->arena_mem), size_t(S->opt.hbm_budget));
   S->d_fs = reinterpret_cast<FitState*>(S->state_mem);
