@@ -383,6 +383,10 @@ def serving(args, uml, G, W):
     budget = args.budget_mb << 20
     s_open = run_server(uml, um, st, k, True, args.slots, budget)
     s_sat = run_server(uml, um, st, k, False, args.slots, budget)
+    # the same saturated stream under a budget below the natural footprint, so
+    # that admission waits for memory
+    s_tight = (run_server(uml, um, st, k, False, args.slots, args.tight_budget_mb << 20)
+               if args.tight_budget_mb > 0 else None)
     empty = {"fits_per_s": 0.0, "p50_ms": 0.0, "p99_ms": 0.0, "elapsed_s": 0.0, "results": []}
     l_sat = run_loop(uml, um, st, kl, False) if kl else empty
     l_open = run_loop(uml, um, st, kl, True) if kl else empty
@@ -415,6 +419,8 @@ def serving(args, uml, G, W):
                              "EDM < 1e-6"),
                 "fits": k, "loop_fits": kl, "slots": args.slots, "hbm_budget_mb": args.budget_mb,
                 "server_open_loop": summary(s_open), "server_saturated": summary(s_sat),
+                "server_saturated_tight_budget": (dict(summary(s_tight), hbm_budget_mb=args.tight_budget_mb)
+                                                  if s_tight else None),
                 "loop_open_loop": summary(l_open), "loop_saturated": summary(l_sat),
                 "capacity_ratio": (round(s_sat["fits_per_s"] / l_sat["fits_per_s"], 2)
                                    if l_sat["fits_per_s"] else None),
@@ -517,6 +523,8 @@ def main():
                     help="4-D model with the P-wave's event-only terms stored per event")
     ap.add_argument("--marginal-events", type=int, default=4_000_000,
                     help="second dataset size for the per-event (marginal) rate; 0: skip")
+    ap.add_argument("--tight-budget-mb", type=int, default=16,
+                    help="budget of a second saturated server run, below the natural footprint; 0: skip")
     ap.add_argument("--rotate", type=int, default=1,
                     help="also time the evaluations over this many distinct datasets in turn "
                          "(a working set beyond the last-level cache); 1: skip")
