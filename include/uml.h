@@ -137,6 +137,10 @@ int uml_model_n_free(const uml_model* m);
 int uml_model_describe(const uml_model* m, char* buf, int32_t len);
 
 /* ---- event data ---------------------------------------------------------
+ * The events x_i of Eq. 1.  A minimisation evaluates the same sample at many
+ * parameter points and host-to-accelerator transfers are an overhead to keep
+ * small (Sec. 2.1), so the events are moved to the device once, here, and
+ * every later evaluation moves only the parameters and its results.
  * n events as a structure of arrays: cols[d] points to n values of dimension
  * d (model order) in storage type dtype.  w (same dtype) is NULL or one
  * weight per event (the weighted NLL -sum w_i ln P_i).  Events are copied
@@ -192,6 +196,18 @@ int uml_eval_nll_grad(const uml_model* m, const uml_data* d, const double* theta
 int uml_eval_nll_grad_dev(const uml_model* m, const uml_data* d, const double* d_theta_all,
                           double* d_out, void* stream);
 
+/* The number of events at which P(x_i | theta) <= 0 or is not finite: the
+ * events outside the domain of Eq. 1's logarithm, which make the NLL +inf.
+ * Every event counts when theta is outside the model's domain (a fraction
+ * outside [0, 1], a Gaussian width <= 0).  The decision is taken in the
+ * model's arithmetic (FP32 per event for UML_MIXED), with the same per-event
+ * arithmetic as the evaluation, so a count > 0 is exactly when an evaluation
+ * at theta_all gives +inf.  A separate pass over the events, not part of the
+ * evaluation: call it after an evaluation returned UML_E_PDF_NONPOSITIVE.
+ * theta_all: host, all parameters.  *n_bad receives the count.  Synchronous. */
+int uml_eval_bad_events(const uml_model* m, const uml_data* d, const double* theta_all, int64_t* n_bad,
+                        void* stream);
+
 /* NLL, gradient and Hessian (n_free x n_free, row-major) in one pass over the
  * events.  w2_free, if not NULL, receives sum_i w_i^2 s_i s_i^T with s_i the
  * per-event score d ln P_i / d theta (the middle of the sandwich covariance
@@ -237,6 +253,10 @@ typedef struct {
   int32_t n_free, n_iter, n_eval, status;
   uint64_t ticket;                               /* server requests              */
   double latency_s;                              /* server: submit -> finished   */
+  int64_t n_bad_events;                          /* status UML_FIT_PDF_NONPOSITIVE:
+                                                    events with P <= 0 or not finite
+                                                    at params (uml_eval_bad_events);
+                                                    0 otherwise                   */
 } uml_fit_result;
 
 void uml_fit_options_default(uml_fit_options* o);

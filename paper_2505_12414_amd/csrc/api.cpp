@@ -108,13 +108,14 @@ DataLayout data_layout(const Plan& P, int64_t n, bool weighted) {
   L.E = events_per_thread(n, P.precision);
   const int64_t tsize = int64_t(L.E) * kBlock;
   L.n_tiles = int(std::max<int64_t>(1, (n + tsize - 1) / tsize));
-  // work area: job | constants | theta | out | counters | partials
+  // work area: job | constants | theta | out | counters | bad-event count | partials
   L.o_job = 0;
   L.o_cst = align_up(L.o_job + sizeof(Job), 256);
   L.o_theta = align_up(L.o_cst + sizeof(ConstBlock), 256);
   L.o_out = align_up(L.o_theta + sizeof(double) * UML_MAX_PARAMS, 256);
   L.o_cnt = align_up(L.o_out + sizeof(double) * (1 + UML_MAX_PARAMS), 256);
-  L.o_part = align_up(L.o_cnt + sizeof(unsigned) * kCounterWords, 256);
+  L.o_bad = align_up(L.o_cnt + sizeof(unsigned) * kCounterWords, 256);
+  L.o_part = align_up(L.o_bad + sizeof(unsigned long long), 256);
   L.bytes_work = L.o_part + sizeof(double) * P.K * (L.n_tiles + kGroups);
   return L;
 }
@@ -136,6 +137,7 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
   d->d_job = reinterpret_cast<Job*>(wbase + L.o_job);
   d->d_theta = reinterpret_cast<double*>(wbase + L.o_theta);
   d->d_out = reinterpret_cast<double*>(wbase + L.o_out);
+  d->d_bad = reinterpret_cast<unsigned long long*>(wbase + L.o_bad);
   Job& J = d->job;
   std::memset(&J, 0, sizeof(J));
   for (int kd = 0; kd < P.ndim; ++kd)
@@ -201,6 +203,34 @@ int check_generation_theta(const uml_model* m, const double* th, const char* fn)
       return set_error(UML_E_INVALID, std::string(fn) + ": a Gaussian width is not positive");
   }
   return UML_OK;
+}
+
+int count_bad_events(const uml_model* m, const uml_data* d, const double* theta, int64_t* n_bad,
+                     hipStream_t s, const char* fn) {
+  const Plan& P = m->plan;
+  unsigned long long h = 0;
+  UML_HIP_CHECK(hipMemcpyAsync(d->d_theta, theta, sizeof(double) * P.npar, hipMemcpyHostToDevice, s));
+  UML_HIP_CHECK(hipMemsetAsync(d->d_bad, 0, sizeof(unsigned long long), s));
+  LaunchArgs a{};
+  a.job0 = d->job;
+  a.grid = d->n_tiles;
+  a.theta = d->d_theta;
+  a.precision = P.precision;
+  a.stream = s;
+  m->family->count(a, d->d_bad);
+  UML_HIP_CHECK(hipGetLastError());
+  UML_HIP_CHECK(hipMemcpyAsync(&h, d->d_bad, sizeof(h), hipMemcpyDeviceToHost, s));
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return set_error(UML_E_HIP, std::string(fn) + ": " + hipGetErrorString(e));
+  *n_bad = int64_t(h);
+  return UML_OK;
+}
+
+int fill_bad_count(const uml_model* m, const uml_data* d, uml_fit_result* r, hipStream_t s,
+                   const char* fn) {
+  r->n_bad_events = 0;
+  if (r->status != UML_FIT_PDF_NONPOSITIVE) return UML_OK;
+  return count_bad_events(m, d, r->params, &r->n_bad_events, s, fn);
 }
 
 GenOut gen_out(const uml_data* d, unsigned int* d_bad) {
@@ -578,6 +608,14 @@ int uml_eval_nll(const uml_model* m, const uml_data* d, const double* theta_all,
 int uml_eval_nll_grad(const uml_model* m, const uml_data* d, const double* theta_all,
                       double* nll, double* grad_free, void* stream) {
   return eval_host(m, d, theta_all, nll, grad_free, stream, "uml_eval_nll_grad");
+}
+
+int uml_eval_bad_events(const uml_model* m, const uml_data* d, const double* theta_all, int64_t* n_bad,
+                        void* stream) {
+  int rc = check_pair(m, d, "uml_eval_bad_events");
+  if (rc) return rc;
+  if (!theta_all || !n_bad) return set_error(UML_E_INVALID, "uml_eval_bad_events: null argument");
+  return count_bad_events(m, d, theta_all, n_bad, static_cast<hipStream_t>(stream), "uml_eval_bad_events");
 }
 
 int uml_eval_nll_grad_dev(const uml_model* m, const uml_data* d, const double* d_theta_all,

@@ -298,9 +298,14 @@ struct Shape {
 // one event
 // ---------------------------------------------------------------------------
 
-template <class S, class T, bool W>
-__device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S::ncst],
-                                      const T (&xref)[S::ndim], T (&acc)[S::K]) {
+// Every factor of every component at one event (shifted coordinates xs):
+// the base-2 exponent E_c and polynomial product V_c of each component, the
+// factor values pv and the event-dependent moment factors mom.
+template <class S, class T>
+__device__ __forceinline__ void components(const T (&x)[S::ndim], const T (&c)[S::ncst],
+                                           const T (&xref)[S::ndim], T (&E)[S::ncomp],
+                                           T (&V)[S::ncomp], T (&mom)[S::K],
+                                           T (&pv)[S::ncomp][kMaxFacPerComp]) {
   constexpr int NC = S::ncomp;
   T xs[S::ndim];
   sfor<S::ndim>([&](auto Id) {
@@ -310,8 +315,6 @@ __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S
     else
       xs[d] = x[d];
   });
-  T E[NC], V[NC], mom[S::K];
-  T pv[NC][kMaxFacPerComp];
   sfor<NC>([&](auto Ic) {
     constexpr int ci = Ic;
     using Cc = typename S::template comp<ci>;
@@ -329,8 +332,13 @@ __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S
     E[ci] = e;
     V[ci] = v;
   });
-  // P = 2^Emax sum_c 2^{E_c - Emax} V_c
-  T ec[NC], Emax;
+}
+
+// The mixture in base-2 log space: P = 2^Emax sum, sum = sum_c Sp_c with
+// Sp_c = 2^{E_c - Emax} V_c = ec_c V_c.
+template <int NC, class T>
+__device__ __forceinline__ void combine(const T (&E)[NC], const T (&V)[NC], T (&ec)[NC], T& Emax,
+                                        T (&Sp)[NC], T& sum) {
   if constexpr (NC == 1) {
     ec[0] = T(1);
     Emax = E[0];
@@ -348,12 +356,23 @@ __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S
 #pragma unroll
     for (int i = 0; i < NC; ++i) ec[i] = k_exp2(E[i] - Emax);
   }
-  T Sp[NC], sum = T(0);
+  sum = T(0);
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
     Sp[i] = ec[i] * V[i];
     sum += Sp[i];
   }
+}
+
+template <class S, class T, bool W>
+__device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S::ncst],
+                                      const T (&xref)[S::ndim], T (&acc)[S::K]) {
+  constexpr int NC = S::ncomp;
+  T E[NC], V[NC], mom[S::K];
+  T pv[NC][kMaxFacPerComp];
+  components<S, T>(x, c, xref, E, V, mom, pv);
+  T ec[NC], Emax, Sp[NC], sum;
+  combine<NC, T>(E, V, ec, Emax, Sp, sum);
   const T l2 = Emax + k_log2(sum);  // log2 P
   const T inv = k_rcp(sum);
   acc[0] += W ? w * l2 : l2;
@@ -759,6 +778,31 @@ __device__ __noinline__ void bfgs_step(const Plan& P, FitState* fs, ConstBlock* 
 // the kernel
 // ---------------------------------------------------------------------------
 
+// One workgroup's arrival at a completion counter shared by `members`
+// workgroups of this launch; true for the workgroup that completes the count.
+// Called by one thread after a workgroup barrier that follows the workgroup's
+// partial stores.  Memory model (HIP's scoped model, agent scope):
+//   * the increment is an agent-scope release: every store that happens
+//     before it (the partials, ordered before it by the barrier) is visible to
+//     any agent-scope acquire that reads the incremented value or a later one;
+//   * the workgroup that completes the count reads the last value of the
+//     counter's release sequence, and its agent-scope acquire fence makes the
+//     partials of every member visible to its later loads; the workgroup
+//     barrier after this call extends that to its other threads;
+//   * the completing workgroup resets the counter for the next launch, which
+//     is ordered after this one by the end of the kernel.
+// On gfx950 the release writes back this XCD's L2 and waits for the
+// workgroup's stores, the acquire invalidates the L2's non-coherent lines.
+__device__ __forceinline__ bool arrive(unsigned* cnt, unsigned members) {
+  const unsigned p = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const bool last = p + 1u == members;
+  if (last) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return last;
+}
+
 template <int K>
 __host__ __device__ constexpr int reduce_parts() {
   int p = 1;
@@ -912,20 +956,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
     double* dst = single ? gpart + int64_t(tid) * kGroups + tile : J.partials + int64_t(tid) * nt + tile;
     __hip_atomic_store(dst, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  // Completion, in two levels (see kGroups).  The barrier before each
-  // counter step waits for this workgroup's coherent stores to complete.
+  // Completion, in two levels (see kGroups), each a release/acquire counter
+  // step (arrive) after a barrier that orders this workgroup's stores.
   const int ng = nt < kGroups ? nt : kGroups;
   const int g = tile % ng;
   double* tot = reinterpret_cast<double*>(red);
   __syncthreads();
   if (single) goto top_level;
-  if (tid == 0) {
-    const unsigned members = unsigned((nt - 1 - g) / ng + 1);
-    unsigned* gcnt = J.counter + g * kCounterStride;
-    const unsigned p = __hip_atomic_fetch_add(gcnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_flag = (p + 1u == members) ? 1 : 0;
-    if (s_flag) __hip_atomic_store(gcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (tid == 0)
+    s_flag = arrive(J.counter + g * kCounterStride, unsigned((nt - 1 - g) / ng + 1)) ? 1 : 0;
   __syncthreads();
   if (!s_flag) return;
   // the last tile of group g sums the group's tiles g, g + ng, .. in order
@@ -938,12 +977,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
                        __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
 top_level:
-  if (tid == 0) {
-    unsigned* top = J.counter + kGroups * kCounterStride;
-    const unsigned q = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_flag = (q + 1u == unsigned(ng)) ? 1 : 0;
-    if (s_flag) __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (tid == 0) s_flag = arrive(J.counter + kGroups * kCounterStride, unsigned(ng)) ? 1 : 0;
   __syncthreads();
   if (!s_flag) return;
   // The last group: the sum over groups, the plan and the constants.  The
@@ -968,6 +1002,58 @@ top_level:
   }
 }
 
+// The events of one tile per workgroup at which P <= 0 or P is not finite
+// (outside the domain of Eq. 1's logarithm), added to *count; every event
+// counts when the point is outside the model's domain.  The same per-event
+// arithmetic as eval_kernel, so it counts exactly the events that make an
+// evaluation +inf.  Not on the evaluation path: the library runs it only
+// after an evaluation returned +inf.
+template <class S, class P>
+__global__ __launch_bounds__(kBlock) void count_kernel(const double* __restrict__ th, const Job J,
+                                                       unsigned long long* __restrict__ count) {
+  using T = typename P::T;
+  constexpr int NC = S::ncomp;
+  __shared__ __align__(16) char buf[sizeof(Plan) + UML_MAX_PARAMS * sizeof(double)];
+  __shared__ __align__(16) ConstBlock s_cb;
+  miss_prologue(J.plan, th, J.npar, buf, &s_cb);
+  T c[S::ncst], xref[S::ndim];
+#pragma unroll
+  for (int i = 0; i < S::ncst; ++i) c[i] = P::consts(&s_cb)[i];
+#pragma unroll
+  for (int d = 0; d < S::ndim; ++d) xref[d] = ((S::shift_mask >> d) & 1u) ? P::xrefs(&s_cb)[d] : T(0);
+  const bool dom = s_cb.domain_ok != 0;
+  const int64_t tsize = int64_t(J.events_per_thread) * kBlock;
+  const int64_t base = int64_t(blockIdx.x) * tsize;
+  const int64_t end = base + tsize < J.n ? base + tsize : J.n;
+  unsigned long long bad = 0;
+  for (int64_t i = base + threadIdx.x; i < end; i += kBlock) {
+    if (!dom) {
+      ++bad;
+      continue;
+    }
+    T x[S::ndim];
+#pragma unroll
+    for (int d = 0; d < S::ndim; ++d) x[d] = load_global(static_cast<const T*>(J.col[d]) + i);
+    T E[NC], V[NC], mom[S::K], pv[NC][kMaxFacPerComp];
+    components<S, T>(x, c, xref, E, V, mom, pv);
+    T ec[NC], Emax, Sp[NC], sum;
+    combine<NC, T>(E, V, ec, Emax, Sp, sum);
+    const T l2 = Emax + k_log2(sum);
+    if (!(sum > T(0)) || !isfinite(l2)) ++bad;
+  }
+  if (bad) atomicAdd(count, bad);
+}
+
+template <class S>
+void launch_count(const LaunchArgs& a, unsigned long long* d_count) {
+  if (a.precision == UML_MIXED)
+    hipLaunchKernelGGL((count_kernel<S, PrecMixed>), dim3(a.grid), dim3(kBlock), 0, a.stream, a.theta, a.job0,
+                       d_count);
+  else
+    hipLaunchKernelGGL((count_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream, a.theta, a.job0,
+                       d_count);
+}
+
 template <class S>
 void launch_eval(const LaunchArgs& a) {
   const double* th0 = a.theta ? a.theta : a.job0.theta;
@@ -981,7 +1067,7 @@ void launch_eval(const LaunchArgs& a) {
 
 template <class S>
 Family make_family() {
-  return Family{S::sig(), S::K, S::ncst, &launch_eval<S>, nullptr};
+  return Family{S::sig(), S::K, S::ncst, &launch_eval<S>, nullptr, &launch_count<S>};
 }
 
 // The compiled catalogue of model shapes.  Components are ordered by their
@@ -1006,7 +1092,7 @@ static const Family* families() {
       make_family<Shape<Comp<PWavePre<3>>>>(),
       make_family<Shape<Comp<Gauss<0>, PWavePre<4>>>>(),
       make_family<Shape<Comp<Exp<0>, Cheb<1, 2>, Cheb<2, 2>, Cheb<3, 2>>, Comp<Gauss<0>, PWavePre<4>>>>(),
-      Family{"", 0, 0, nullptr, nullptr},
+      Family{"", 0, 0, nullptr, nullptr, nullptr},
   };
   return table;
 }

@@ -442,6 +442,7 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
     for (int i = 0; i < n; ++i) {
       std::memset(&out[i], 0, sizeof(uml_fit_result));
       int rc = newton_fit(m, const_cast<uml_data*>(ds[i]), starts + size_t(i) * P.npar, o, &out[i], fn);
+      if (rc == UML_OK) rc = fill_bad_count(m, ds[i], &out[i], nullptr, fn);
       if (rc != UML_OK) return rc;
     }
     return UML_OK;
@@ -540,12 +541,14 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
     std::vector<double> theta(F.theta, F.theta + P.npar);
     if (!F.done)
       for (int a = 0; a < P.nfree; ++a) theta[P.free_idx[a]] = F.x[a];
+    int rc = UML_OK;
     if (r.status == UML_FIT_PDF_NONPOSITIVE) {
       for (int k = 0; k < P.npar; ++k) r.params[k] = theta[k];
       r.nll = INFINITY;
-      continue;
+    } else {
+      rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o, &r, nullptr, fn);
     }
-    int rc = finish_fit(m, const_cast<uml_data*>(ds[i]), theta, o, &r, nullptr, fn);
+    if (rc == UML_OK) rc = fill_bad_count(m, ds[i], &r, nullptr, fn);
     if (rc != UML_OK) return rc;
   }
   return UML_OK;

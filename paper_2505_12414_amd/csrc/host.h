@@ -40,6 +40,7 @@ struct uml_data {
   uml::Job* d_job = nullptr;
   double* d_theta = nullptr;        // staging for host theta
   double* d_out = nullptr;          // [1 + nfree]
+  unsigned long long* d_bad = nullptr;  // count of events with P <= 0 (count pass)
   void* d_hwork = nullptr;          // Hessian workspace (allocated on first use)
   int hess_tiles = 0;
   double* h_stage = nullptr;        // pinned host staging (a block of the process pool)
@@ -66,7 +67,7 @@ struct DataLayout {
   int E, n_tiles;
   int64_t stride;
   size_t bytes_events, bytes_work;
-  size_t o_job, o_cst, o_theta, o_out, o_cnt, o_part;
+  size_t o_job, o_cst, o_theta, o_out, o_cnt, o_bad, o_part;
 };
 int convert_events(const Plan& P, int64_t n, const void* const* cols, int32_t dtype, const void* w,
                    std::vector<char>& host, const char* fn);
@@ -76,6 +77,13 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
 hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>& host, hipStream_t s);
 hipError_t data_init_work(uml_data* d, const DataLayout& L, hipStream_t s);
 int check_generation_theta(const uml_model* m, const double* theta, const char* fn);
+// Events with P <= 0 or not finite at theta (host, all parameters); synchronous.
+int count_bad_events(const uml_model* m, const uml_data* d, const double* theta, int64_t* n_bad,
+                     hipStream_t s, const char* fn);
+// Sets r->n_bad_events for a result whose status is UML_FIT_PDF_NONPOSITIVE (the
+// count at r->params), 0 otherwise.
+int fill_bad_count(const uml_model* m, const uml_data* d, uml_fit_result* r, hipStream_t s,
+                   const char* fn);
 GenOut gen_out(const uml_data* d, unsigned int* d_bad);
 size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles);
 double* pinned_stage_get();

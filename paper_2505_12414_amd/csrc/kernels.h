@@ -35,6 +35,8 @@ struct Family {
   int ncst;    // kernel constants
   void (*eval)(const LaunchArgs&);
   void (*hess)(const LaunchArgs&, double* hpart, int nfree);
+  // events with P <= 0 or not finite at a.theta, added to *d_count
+  void (*count)(const LaunchArgs&, unsigned long long* d_count);
 };
 
 // Returns the compiled family for a signature, or nullptr.

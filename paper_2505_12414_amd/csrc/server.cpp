@@ -404,6 +404,8 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
       r.status = H.fs.status;
       r.nll = INFINITY;
       for (int k = 0; k < m->plan.npar; ++k) r.params[k] = sl.req.start[k];
+      rc = fill_bad_count(m, &sl.data, &r, S->stream, "server");
+      if (rc != UML_OK) return rc;
       release_slot(S, sl);
       push_result(S, r, sl.req);
       continue;
@@ -474,6 +476,8 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
       int rc = finish_fit(m, &sl.data, theta, S->opt.fit, &r, S->stream, "server");
       if (rc != UML_OK) return rc;
     }
+    int rc = fill_bad_count(m, &sl.data, &r, S->stream, "server");
+    if (rc != UML_OK) return rc;
     release_slot(S, sl);
     push_result(S, r, sl.req);
     std::lock_guard<std::mutex> lk(S->mu);

@@ -86,7 +86,7 @@ class uml_fit_result(C.Structure):
                 ("cov", C.c_double * (MAX_PARAMS * MAX_PARAMS)), ("nll", C.c_double),
                 ("edm", C.c_double), ("n_free", C.c_int32), ("n_iter", C.c_int32),
                 ("n_eval", C.c_int32), ("status", C.c_int32), ("ticket", C.c_uint64),
-                ("latency_s", C.c_double)]
+                ("latency_s", C.c_double), ("n_bad_events", C.c_int64)]
 
 
 class uml_server_options(C.Structure):
@@ -126,6 +126,7 @@ SIGNATURES = {
     "uml_eval_nll_grad": (C.c_int, [_P, _P, _DP, _DP, _DP, _P]),
     "uml_eval_nll_grad_dev": (C.c_int, [_P, _P, _P, _P, _P]),
     "uml_eval_hessian": (C.c_int, [_P, _P, _DP, _DP, _DP, _DP, _DP, _P]),
+    "uml_eval_bad_events": (C.c_int, [_P, _P, _DP, C.POINTER(C.c_int64), _P]),
     "uml_fit_options_default": (None, [C.POINTER(uml_fit_options)]),
     "uml_fit": (C.c_int, [_P, _P, _DP, C.POINTER(uml_fit_options), C.POINTER(uml_fit_result)]),
     "uml_fit_batch": (C.c_int, [_P, C.POINTER(_P), C.c_int32, _DP, C.POINTER(uml_fit_options),
@@ -373,6 +374,16 @@ def uml_eval_nll_grad(model, data, theta=None, stream=None, allow_nonpositive=Tr
     return out.value, g[:model.n_free].copy()
 
 
+def uml_eval_bad_events(model, data, theta=None, stream=None):
+    """Events at which P <= 0 or P is not finite (all of them outside the
+    model's domain)."""
+    th = _theta(model, theta)
+    out = C.c_int64()
+    check(lib().uml_eval_bad_events(model.handle, data.handle, _dptr(th), C.byref(out),
+                                    _stream_ptr(stream)))
+    return int(out.value)
+
+
 def uml_eval_nll_grad_dev(model, data, d_theta, d_out, stream=None):
     """Stream-ordered: d_theta (float64 CUDA tensor, n_params) -> d_out
     (float64 CUDA tensor, 1 + n_free).  stream: torch.cuda.Stream, raw
@@ -419,7 +430,7 @@ def result_dict(model, r):
             "cov": np.array(r.cov[:nf * nf]).reshape(nf, nf), "nll": r.nll, "edm": r.edm,
             "n_iter": r.n_iter, "n_eval": r.n_eval, "status": r.status,
             "status_name": FIT_STATUS.get(r.status, str(r.status)), "ticket": r.ticket,
-            "latency_s": r.latency_s}
+            "latency_s": r.latency_s, "n_bad_events": r.n_bad_events}
 
 
 def uml_fit(model, data, start=None, **opts):
