@@ -165,3 +165,28 @@ def gen_pwave3d(n, seed, ang=(0.6, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0), dtype=np.
 def uniform_weights(n, seed, lo=0.5, hi=1.5, dtype=np.float32):
     """Per-event weights w ~ U(lo, hi), independent of the events."""
     return _rng(seed).uniform(lo, hi, size=n).astype(dtype)
+
+
+def gen_mix1d(n, seed, ncomp, dtype=np.float64):
+    """The 1-D mixtures of three and four components used by the parity
+    tests, as nested sums on [5.0, 5.6]:
+        f1 G(5.25, 0.02) + (1 - f1) [f2 G(5.35, 0.04) + (1 - f2) E(-1.5)]       (3)
+        f1 G(5.25, 0.02) + (1 - f1) [f2 G(5.35, 0.04)
+                                     + (1 - f2) (f3 E(-1.5) + (1 - f3) C(0.2))]  (4)
+    with f1 = 0.3, f2 = 0.4, f3 = 0.5.  Each event picks its component by
+    the fractions, then draws from it; returns shape (1, n)."""
+    lo, hi = 5.0, 5.6
+    rng = _rng(seed)
+    u = rng.uniform(size=(3, n))
+    g1 = u[0] < 0.3
+    g2 = ~g1 & (u[1] < 0.4)
+    rest = ~g1 & ~g2
+    ex = rest & (u[2] < 0.5) if ncomp == 4 else rest
+    ch = rest & ~ex
+    m = np.empty(n, dtype=np.float64)
+    m[g1] = trunc_normal(rng, int(g1.sum()), 5.25, 0.02, lo, hi)
+    m[g2] = trunc_normal(rng, int(g2.sum()), 5.35, 0.04, lo, hi)
+    m[ex] = trunc_exponential(rng, int(ex.sum()), -1.5, lo, hi)
+    if ncomp == 4:
+        m[ch] = cheb_shape(rng, int(ch.sum()), (0.2,), lo, hi)
+    return to_storage(m, lo, hi, dtype).reshape(1, n)

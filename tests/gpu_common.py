@@ -82,6 +82,8 @@ def rng_events(desc, n, seed, dtype):
         return G.gen_mass1d(n, seed, dtype=dtype)
     if names == ["ctl", "ctk", "phi"]:
         return G.gen_pwave3d(n, seed, dtype=dtype)
+    if names == ["m"] and len(desc["params"]) in (7, 9) and desc["params"][0]["name"] == "mu1":
+        return G.gen_mix1d(n, seed, 3 if len(desc["params"]) == 7 else 4, dtype=dtype)
     rng = np.random.default_rng(seed)
     cols = [G.to_storage(rng.uniform(d["lo"], d["hi"], n), d["lo"], d["hi"], dtype)
             for d in desc["dims"]]

@@ -16,10 +16,10 @@ from oracle_pool import oracle_points, workers
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(1_000_000, 1000), (10_000_000, 100)]
+CASES = [(1_000_000, 1000), (10_000_000, 1000)]
 
 
-@pytest.mark.timeout(900)
+@pytest.mark.timeout(1200)
 @pytest.mark.parametrize("n,k", CASES, ids=[f"{c[0]}x{c[1]}" for c in CASES])
 def test_random_points_mixed_and_fp64(n, k, tmp_path):
     desc = W.mass1d()
@@ -38,7 +38,7 @@ def test_random_points_mixed_and_fp64(n, k, tmp_path):
         for th, (nll_o, g_o, _) in zip(pts, ref):
             nll_g, g_g = uml.uml_eval_nll_grad(um, ud, th)
             rel.append(abs(nll_g - nll_o) / abs(nll_o))
-            gerr.append(np.abs(g_g - g_o) * sig[om.free])
+            gerr.append(np.abs(g_g - g_o) * sig)  # sig is over the free parameters
         rel, gerr = np.array(rel), np.array(gerr)
         say(f"  {precision}: NLL rel err max {rel.max():.2e} median {np.median(rel):.2e}; "
             f"grad err/sigma max {gerr.max(0)} median {np.median(gerr, 0)}")
