@@ -14,8 +14,10 @@ static __device__ __forceinline__ float k_log2(float x) { return __builtin_amdgc
 static __device__ __forceinline__ float k_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 static __device__ __forceinline__ float k_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 static __device__ __forceinline__ void k_sincos(float phi, float& s, float& c) {
-  // the hardware sine and cosine take their argument in revolutions
-  const float t = phi * 0.15915494309189535f;
+  // the hardware sine and cosine take their argument in revolutions:
+  // t = phi / (2 pi) with 1/(2 pi) as an FP32 pair (its nearest FP32 value
+  // alone is 4e-8 small, a scale error that every event would share)
+  const float t = fmaf(phi, 0x1.45f306p-3f, phi * 0x1.b9391p-28f);
   s = __builtin_amdgcn_sinf(t);
   c = __builtin_amdgcn_cosf(t);
 }

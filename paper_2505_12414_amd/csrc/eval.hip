@@ -79,9 +79,18 @@ struct PrecF64 {
 //   polynomial-type factors return their value v;
 //   m[] receives the event-dependent factors of the moment sums.
 // Kernel constants c[] are written by the prologue (see compute_constants).
+// In mixed precision a constant through which every event depends on a
+// parameter comes as an FP32 pair (hi, lo), and the lo part enters before
+// the rounding of a value that varies from event to event, so its effect is
+// not lost to the same rounding at every event.
 // ---------------------------------------------------------------------------
 
-// Gaussian in dimension D.  c = {mu - xref, log2(e) / (2 sigma^2)}.
+template <class T>
+constexpr bool kF32 = std::is_same<T, float>::value;
+
+// Gaussian in dimension D.  c = {c0_hi, c1_hi, c1_lo, k2}: the exponent
+// -c1 (d - c0_lo)^2 with c1 = log2(e) / (2 sigma^2), d = x' - c0_hi exact and
+// k2 = 2 c1 c0_lo (FP32 only; in FP64 c0_hi = mu - xref, c0_lo = 0).
 template <int D>
 struct Gauss {
   static constexpr int kind = FK_GAUSS, order = 0;
@@ -95,6 +104,7 @@ struct Gauss {
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
     const T d = xs[D] - c[0];
     const T d2 = d * d;
+    if constexpr (kF32<T>) e = fma(d, fma(-c[2], d, c[3]), e);
     e = fma(-d2, c[1], e);
     m[0] = d;
     m[1] = d2;
@@ -102,7 +112,7 @@ struct Gauss {
   }
 };
 
-// Exponential e^{lambda x} in dimension D.  c = {lambda log2(e)}.
+// Exponential e^{lambda x} in dimension D.  c = {lambda log2(e)} as a pair.
 template <int D>
 struct Exp {
   static constexpr int kind = FK_EXP, order = 0;
@@ -114,14 +124,16 @@ struct Exp {
   static std::string sig() { return "E" + std::to_string(D); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
+    if constexpr (kF32<T>) e = fma(xs[D], c[1], e);
     e = fma(xs[D], c[0], e);
     m[0] = xs[D];
     (void)v;
   }
 };
 
-// Chebyshev series of order N in dimension D, normalised:
-// v = (1 + sum c_j T_j(u)) / N_C.  c = {s, t, 1/N_C, c_1/N_C .. c_N/N_C}, u = x s + t.
+// Chebyshev series of order N in dimension D without its norm (which is in
+// the component's prefactor): v = sgn (1 + sum c_j T_j(u)), sgn the sign of
+// the norm.  c = {s_hi, s_lo, t, sgn, sgn c_1 .. sgn c_N}, u = x s + t.
 template <int D, int N>
 struct Cheb {
   static constexpr int kind = FK_CHEB, order = N;
@@ -133,7 +145,7 @@ struct Cheb {
   static std::string sig() { return "C" + std::to_string(D) + "." + std::to_string(N); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
-    const T u = fma(xs[D], c[0], c[1]);
+    const T u = kF32<T> ? fma(xs[D], c[0], fma(xs[D], c[1], c[2])) : fma(xs[D], c[0], c[2]);
     T tj[N + 1];
     tj[0] = T(1);
     tj[1] = u;
@@ -142,10 +154,10 @@ struct Cheb {
 #pragma unroll
       for (int j = 2; j <= N; ++j) tj[j] = fma(u2, tj[j - 1], -tj[j - 2]);
     }
-    T val = c[2];
+    T val = c[3];
 #pragma unroll
     for (int j = 1; j <= N; ++j) {
-      val = fma(c[2 + j], tj[j], val);
+      val = fma(c[3 + j], tj[j], val);
       m[j - 1] = tj[j];
     }
     v = val;
@@ -178,13 +190,14 @@ __device__ __forceinline__ void pwave_terms(T cl, T ck, T ph, T& u0, T (&m)[8]) 
   m[7] = skl2 * (sp * cp);               // S9 / 2
 }
 
-// P-wave angular density (Eq. 4) in dimensions (cos theta_l, cos theta_K, phi).
-// Written as  v = c0 u0 + c1 (u1 - u0) + sum_k c_{k+1} b_k  with
+// P-wave angular density (Eq. 4) in dimensions (cos theta_l, cos theta_K, phi),
+// without its factor 9/(32 pi) (in the component's prefactor).
+// Written as  v = u0 + c0 (u1 - u0) + sum_k c_k b_k  with
 //   u0 = sin^2 K (3/4 + cos 2l / 4) = sin^2 K (1 - sin^2 l / 2),
 //   u1 = cos^2 K (1 - cos 2l) = 2 cos^2 K sin^2 l,
 //   b  = the S3, S4, S5, AFB, S7, S8, S9 terms without their constant
 //        factors (1, 4, 2, 4/3, 2, 4, 2), which the prologue folds into
-//        c = 9/(32 pi) * {1, FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8, 2 S9};
+//        c = {FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8, 2 S9};
 // moments m = {u1 - u0, b_S3, .., b_S9}.  sin K sin l = sqrt(sin^2 K sin^2 l)
 // needs one square root; 1 - c^2 is one FMA (correctly rounded).
 template <int D0, int D1, int D2>
@@ -202,11 +215,11 @@ struct PWave {
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
     T u0, mm[8];
     pwave_terms(xs[D0], xs[D1], xs[D2], u0, mm);
-    T val = c[0] * u0;
+    T val = u0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       m[k] = mm[k];
-      val = fma(c[1 + k], mm[k], val);
+      val = fma(c[k], mm[k], val);
     }
     v = val;
     (void)e;
@@ -227,11 +240,11 @@ struct PWavePre {
   static std::string sig() { return "Q" + std::to_string(B); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
-    T val = c[0] * xs[B];
+    T val = xs[B];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       m[k] = xs[B + 1 + k];
-      val = fma(c[1 + k], m[k], val);
+      val = fma(c[k], m[k], val);
     }
     v = val;
     (void)e;
@@ -241,18 +254,18 @@ struct PWavePre {
 template <class... F>
 struct Comp {
   static constexpr int nfac = sizeof...(F);
-  static constexpr int ncst = 1 + (F::ncst + ... + 0);
+  static constexpr int ncst = kCompCst + (F::ncst + ... + 0);
   static constexpr int nmom = 1 + (F::nmom + ... + 0);
   static constexpr int maxdim = std::max({F::maxdim...});
   static constexpr unsigned shift_mask = (F::shift_mask | ... | 0u);
   static constexpr bool pre = (F::pre || ... || false);
   template <int I>
   using fac = typename TypeAt<I, F...>::type;
-  // offsets inside the component's block: constants after log2 K_c,
-  // moments after r_c
+  // offsets inside the component's block: constants after log2 K_c (a
+  // pair), moments after r_c
   static constexpr int cst_off(int i) {
     constexpr int a[] = {F::ncst...};
-    int o = 1;
+    int o = kCompCst;
     for (int k = 0; k < i; ++k) o += a[k];
     return o;
   }
@@ -319,7 +332,9 @@ __device__ __forceinline__ void components(const T (&x)[S::ndim], const T (&c)[S
     constexpr int ci = Ic;
     using Cc = typename S::template comp<ci>;
     constexpr int cb = S::cst_base(ci), mb = S::mom_base(ci);
-    T e = c[cb];  // log2 K_c
+    // log2 K_c: the exponent starts from its lo part and takes the hi part
+    // last (FP32), so the lo part is added before the final rounding
+    T e = kF32<T> ? c[cb + 1] : c[cb];
     T v = T(1);
     sfor<Cc::nfac>([&](auto If) {
       constexpr int fi = If;
@@ -329,7 +344,7 @@ __device__ __forceinline__ void components(const T (&x)[S::ndim], const T (&c)[S
       pv[ci][fi] = pval;
       if constexpr (!Fc::expo) v *= pval;
     });
-    E[ci] = e;
+    E[ci] = kF32<T> ? e + c[cb] : e;
     V[ci] = v;
   });
 }

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "devmath.h"
 #include "hess.h"
@@ -102,6 +103,13 @@ __device__ __forceinline__ T ld(const void* col, int64_t i) {
   return static_cast<const T*>(col)[i];
 }
 
+// The kernel constants of the event arithmetic's precision (the FP32 set,
+// with its pairs, for mixed precision).
+__device__ __forceinline__ const float* kconsts(const ConstBlock& cb, float) { return cb.f; }
+__device__ __forceinline__ const double* kconsts(const ConstBlock& cb, double) { return cb.d; }
+template <class T>
+constexpr bool kHessF32 = std::is_same<T, float>::value;
+
 // Evaluates one event and writes its staged row.  A parameter belongs to at
 // most one unit of a component (the Hessian plan refuses models where it does
 // not), so each entry of l_c is written once after the zeroing: plain stores,
@@ -119,7 +127,8 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
   for (int c = 0; c < nc; ++c) {
     const CompPlan& C = P.comp[c];
     T* l = lv + c * nf;
-    T e = T(cb.d[C.cst_lk2]);
+    const T* kcomp = kconsts(cb, T(0)) + C.cst_lk2;
+    T e = kHessF32<T> ? kcomp[1] : kcomp[0];  // log2 K_c: lo part first (see eval.hip)
     T v = T(1);
     for (int k = 0; k < C.nfrac; ++k) {
       const int fp = P.free_pos[C.frac_par[k]];
@@ -128,28 +137,32 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
     for (int j = 0; j < C.nfac; ++j) {
       const int fi = C.fac[j];
       const FactorPlan& F = P.fac[fi];
-      const double* kc = cb.d + F.cst;
+      const T* kc = kconsts(cb, T(0)) + F.cst;
       const double* ec = cb.e + F.ecst;
       T* qf = q + H.q_off[fi];
       switch (F.kind) {
         case FK_GAUSS: {
           const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
-          const T d = x - T(kc[0]);
-          e = fma(-d * d, T(kc[1]), e);
+          const T d = x - kc[0];
+          if constexpr (kHessF32<T>) e = fma(d, fma(-kc[2], d, kc[3]), e);
+          e = fma(-d * d, kc[1], e);
           const T lm = fma(d, T(ec[0]), T(ec[1]));
-          const T ls = fma(d * d, T(ec[2]), T(ec[3]));
+          const T ls = fma(d * d, T(ec[2]), fma(d, T(ec[4]), T(ec[3])));
           const int pm = P.free_pos[F.par[0]], ps = P.free_pos[F.par[1]];
           if (pm >= 0) l[pm] = lm;
           if (ps >= 0) l[ps] = ls;
           const T is2 = T(ec[0]), is3 = T(ec[2]);
+          // the centre's remainder c0_lo = k2 / (2 c1) (zero in FP64)
+          const T dt = kHessF32<T> ? d - kc[3] / (T(2) * (kc[1] + kc[2])) : d;
           qf[0] = lm * lm - is2 - T(hc[4 * fi + 0]);
-          qf[1] = lm * ls - T(2) * d * is3 - T(hc[4 * fi + 1]);
-          qf[2] = ls * ls - T(3) * d * d * is2 * is2 + is2 - T(hc[4 * fi + 2]);
+          qf[1] = lm * ls - T(2) * dt * is3 - T(hc[4 * fi + 1]);
+          qf[2] = ls * ls - T(3) * dt * dt * is2 * is2 + is2 - T(hc[4 * fi + 2]);
           break;
         }
         case FK_EXP: {
           const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
-          e = fma(x, T(kc[0]), e);
+          if constexpr (kHessF32<T>) e = fma(x, kc[1], e);
+          e = fma(x, kc[0], e);
           const T lx = x + T(ec[1]);
           const int p = P.free_pos[F.par[0]];
           if (p >= 0) l[p] = lx;
@@ -159,13 +172,13 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
         case FK_CHEB: {
           const int k = F.order;
           const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
-          const T u = fma(x, T(kc[0]), T(kc[1]));
+          const T u = kHessF32<T> ? fma(x, kc[0], fma(x, kc[1], kc[2])) : fma(x, kc[0], kc[2]);
           T tj[kMaxCheb + 1];
           tj[0] = T(1);
           tj[1] = u;
           for (int jj = 2; jj <= k; ++jj) tj[jj] = T(2) * u * tj[jj - 1] - tj[jj - 2];
-          T val = T(kc[2]);
-          for (int jj = 1; jj <= k; ++jj) val = fma(T(kc[2 + jj]), tj[jj], val);
+          T val = kc[3];
+          for (int jj = 1; jj <= k; ++jj) val = fma(kc[3 + jj], tj[jj], val);
           v *= val;
           const T iv = T(1) / val;
           for (int jj = 0; jj < k; ++jj) {
@@ -197,8 +210,8 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           m[5] = w * sp;
           m[6] = wc * sp;
           m[7] = skl2 * (sp * cp);
-          T val = T(kc[0]) * u0;
-          for (int kk = 0; kk < 8; ++kk) val = fma(T(kc[1 + kk]), m[kk], val);
+          T val = u0;
+          for (int kk = 0; kk < 8; ++kk) val = fma(kc[kk], m[kk], val);
           v *= val;
           const T iv = T(1) / val;
           for (int kk = 0; kk < 8; ++kk) {
@@ -209,7 +222,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
         }
       }
     }
-    E[c] = e;
+    E[c] = kHessF32<T> ? e + kcomp[0] : e;
     V[c] = v;
   }
   T Emax = E[0];

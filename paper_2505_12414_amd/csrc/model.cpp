@@ -309,7 +309,8 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
       return UML_E_UNSUPPORTED;
     }
     C.nfrac = (int)t.frac.size();
-    C.cst_lk2 = cst++;
+    C.cst_lk2 = cst;
+    cst += kCompCst;
     C.slot_r = mom++;
     for (int k = 0; k < C.nfrac; ++k) {
       C.frac_par[k] = t.frac[k].first;
@@ -340,11 +341,12 @@ int build_plan(const uml_model_desc* d, Plan& P, std::string& err) {
       F.mom = mom;
       // gradient terms (see EpiTerm); R = the component's responsibility sum
       switch (F.kind) {
-        case FK_GAUSS:  // mu: M_d, R; sigma: M_dd, R
+        case FK_GAUSS:  // mu: M_d, R; sigma: M_dd, R, M_d
           gterms.push_back({F.par[0], mom, ecst});
           gterms.push_back({F.par[0], C.slot_r, ecst + 1});
           gterms.push_back({F.par[1], mom + 1, ecst + 2});
           gterms.push_back({F.par[1], C.slot_r, ecst + 3});
+          gterms.push_back({F.par[1], mom, ecst + 4});
           break;
         case FK_EXP:
           gterms.push_back({F.par[0], mom, ecst});

@@ -88,12 +88,33 @@ static constexpr double kInvSqrt2Pi = 0.39894228040143267794;
 
 // Output of one factor's kernel constants, written in both precisions from
 // registers (the FP32 copies are what the mixed-precision kernels load).
+//   put:       the same value in both sets;
+//   put2:      different values in the FP64 and FP32 sets;
+//   put_pair:  v in the FP64 set (and 0 after it); in the FP32 set its
+//              nearest FP32 value and the remainder, also in FP32, so that
+//              the two carry v to about 2^-48 relative.
+// A constant rounded once to FP32 is off by up to 2^-24 relative at every
+// event alike: summed over N events such an error grows as N while the
+// statistical uncertainty shrinks as 1/sqrt(N), so the constants through
+// which every event's value depends on a parameter go to the kernels as
+// pairs.
 struct KOut {
   double* d;
   float* f;
   __device__ __forceinline__ void put(int i, double v) const {
     d[i] = v;
     f[i] = float(v);
+  }
+  __device__ __forceinline__ void put2(int i, double vd, double vf) const {
+    d[i] = vd;
+    f[i] = float(vf);
+  }
+  __device__ __forceinline__ void put_pair(int i, double v) const {
+    const float hi = float(v);
+    d[i] = v;
+    d[i + 1] = 0.0;
+    f[i] = hi;
+    f[i + 1] = float(v - double(hi));
   }
 };
 
@@ -103,9 +124,23 @@ struct KOut {
 //   d ln g / d mu    = d / sigma^2 - (phi(za) - phi(zb)) / (sigma D)
 //   d ln g / d sigma = d^2 / sigma^3 - 1/sigma - (za phi(za) - zb phi(zb)) / (sigma D)
 // (1/sigma and 1/D are formed once: the divisions are long dependent chains.)
+//
+// Mixed precision: the events are FP32 values shifted by xref (an FP32
+// value), exactly, so x' lies on the grid G = ulp(xref) / 2 wherever
+// x is within a factor two of xref.  The centre c0 = mu - xref is split
+// into c0_hi, a multiple of G, and the rest c0_lo (below G / 2): the
+// kernel's d = x' - c0_hi is then exact, and
+//   -c1 (d - c0_lo)^2 = -c1 d^2 + k2 d - c1 c0_lo^2,   k2 = 2 c1 c0_lo,
+// with c1 = log2(e) / (2 sigma^2) as an FP32 pair and the last term folded
+// into the prefactor.  (Rounding d itself would shift the centre by the
+// same amount at every event of a binade of |d|.)  The moments are sums of
+// d and d^2, so the epilogue coefficients take the shift by c0_lo:
+//   sum r (d - c0_lo)   = M_d - c0_lo R,
+//   sum r (d - c0_lo)^2 = M_dd - 2 c0_lo M_d + c0_lo^2 R.
+// In FP64 c0_hi = c0 and c0_lo = 0.
 static __device__ __forceinline__ bool gauss_constants(const FactorPlan& F, const double* __restrict__ th,
                                                        const double* tr, const KOut& k, double* ec,
-                                                       double* lnorm2) {
+                                                       double* lnorm2, bool mixed) {
   const double a = F.lo[0], b = F.hi[0];
   const double mu = th[F.par[0]], sg = th[F.par[1]];
   const double za = (a - mu) / sg, zb = (b - mu) / sg;  // as in stage 1
@@ -113,13 +148,23 @@ static __device__ __forceinline__ bool gauss_constants(const FactorPlan& F, cons
   const double D = phi_diff_from(za, zb, tr[0], tr[1]);
   const double iD = 1.0 / D;
   const double pa = tr[2] * kInvSqrt2Pi, pb = tr[3] * kInvSqrt2Pi;
-  k.put(0, mu - F.xref);
-  k.put(1, 0.5 * kLog2e * (isg * isg));
-  *lnorm2 = -p_log2(sg * kSqrt2Pi * D);
-  ec[0] = isg * isg;                                 // x sum r d
-  ec[1] = -(pa - pb) * (isg * iD);                   // x sum r
-  ec[2] = isg * isg * isg;                           // x sum r d^2
-  ec[3] = -(isg + (za * pa - zb * pb) * (isg * iD)); // x sum r
+  const double c0 = mu - F.xref, c1 = 0.5 * kLog2e * (isg * isg);
+  double c0_hi = c0;
+  if (mixed) {
+    const double G = F.xref != 0.0 ? ldexp(1.0, ilogb(F.xref) - 24) : 0.0;
+    c0_hi = double(float(G > 0.0 ? rint(c0 / G) * G : c0));
+  }
+  const double c0_lo = c0 - c0_hi;
+  k.put2(0, c0, c0_hi);
+  k.put_pair(1, c1);
+  k.put2(3, 0.0, 2.0 * c1 * c0_lo);
+  *lnorm2 = -p_log2(sg * kSqrt2Pi * D) - c1 * c0_lo * c0_lo;
+  const double is2 = isg * isg, is3 = is2 * isg;
+  ec[0] = is2;                                                        // x sum r d
+  ec[1] = -(pa - pb) * (isg * iD) - c0_lo * is2;                      // x sum r
+  ec[2] = is3;                                                        // x sum r d^2
+  ec[3] = -(isg + (za * pa - zb * pb) * (isg * iD)) + c0_lo * c0_lo * is3;  // x sum r
+  ec[4] = -2.0 * c0_lo * is3;                                         // x sum r d
   return sg > 0.0;
 }
 
@@ -134,7 +179,7 @@ static __device__ __forceinline__ bool exp_constants(const FactorPlan& F, const 
                                                      double* lnorm2) {
   const double a = F.lo[0], b = F.hi[0], xr = F.xref, L = b - a;
   const double lam = th[F.par[0]];
-  k.put(0, lam * kLog2e);
+  k.put_pair(0, lam * kLog2e);
   ec[0] = 1.0;
   if (lam == 0.0) {
     *lnorm2 = -p_log2(L);
@@ -155,11 +200,14 @@ static __device__ __forceinline__ bool exp_constants(const FactorPlan& F, const 
 }
 
 // Chebyshev series 1 + sum_j c_j T_j(u) on [a, b], u = (2x - a - b)/(b - a),
-// with norm N_C = (b - a) + sum_{j even} c_j (b - a)/(1 - j^2).
-//   d ln p / d c_j = T_j / (1 + sum c T) - J_j / N_C,  J_j = d N_C / d c_j
+// with norm N_C = (b - a) + sum_{j even} c_j (b - a)/(1 - j^2).  The kernel
+// evaluates v = sgn (1 + sum c_j T_j), sgn the sign of N_C, with u = x s + t
+// (the scale s = 2/(b - a) as a pair); 1/|N_C| goes to the prefactor.
+//   d ln p / d c_j = sgn T_j / v - J_j / N_C,  J_j = d N_C / d c_j
 // Unrolled to the maximum order, so the coefficient reads go out together.
+// N_C = 0 is outside the domain.
 static __device__ __forceinline__ bool cheb_constants(const FactorPlan& F, const double* __restrict__ th,
-                                                      const KOut& k, double* ec) {
+                                                      const KOut& k, double* ec, double* lnorm2) {
   const double a = F.lo[0], b = F.hi[0], xr = F.xref, L = b - a;
   const int n = F.order;
   double J[kMaxCheb], c[kMaxCheb];
@@ -173,45 +221,46 @@ static __device__ __forceinline__ bool cheb_constants(const FactorPlan& F, const
 #pragma unroll
   for (int j = 0; j < kMaxCheb; ++j)
     if (j < n) N += c[j] * J[j];
-  const double iL = 1.0 / L, iN = 1.0 / N;
-  k.put(0, 2.0 * iL);
-  k.put(1, (2.0 * xr - a - b) * iL);
-  k.put(2, iN);
+  const double iL = 1.0 / L, iN = 1.0 / N, sgn = N < 0.0 ? -1.0 : 1.0;
+  k.put_pair(0, 2.0 * iL);
+  k.put(2, (2.0 * xr - a - b) * iL);
+  k.put(3, sgn);
 #pragma unroll
   for (int j = 0; j < kMaxCheb; ++j)
     if (j < n) {
-      k.put(3 + j, c[j] * iN);
-      ec[j] = iN;              // x sum q T_j
+      k.put(4 + j, sgn * c[j]);
+      ec[j] = sgn;             // x sum q T_j
       ec[n + j] = -J[j] * iN;  // x sum r
     }
-  return true;
+  *lnorm2 = -p_log2(fabs(N));
+  return N != 0.0;
 }
 
-// P-wave density (Eq. 4): coefficients 9/(32 pi) {1, FL, S3, 4 S4, 2 S5,
-// 4/3 AFB, 2 S7, 4 S8, 2 S9}; d ln A / d S_k = 9/(32 pi) s_k b_k / A.
+// P-wave density (Eq. 4), evaluated without its factor 9/(32 pi), which goes
+// to the prefactor: coefficients {FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8,
+// 2 S9}; d ln A / d S_k = s_k b_k / A' with A' the density without 9/(32 pi).
 static __device__ __forceinline__ void pwave_constants(const FactorPlan& F, const double* __restrict__ th,
-                                                       const KOut& k, double* ec) {
-  const double kap = 9.0 / (32.0 * M_PI);
+                                                       const KOut& k, double* ec, double* lnorm2) {
   const double scale[8] = {1.0, 1.0, 4.0, 2.0, 4.0 / 3.0, 2.0, 4.0, 2.0};
-  k.put(0, kap);
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    k.put(1 + i, kap * scale[i] * th[F.par[i]]);
-    ec[i] = kap * scale[i];
+    k.put(i, scale[i] * th[F.par[i]]);
+    ec[i] = scale[i];
   }
+  *lnorm2 = p_log2(9.0 / (32.0 * M_PI));
 }
 
 // Stage 2 for one factor: kernel constants, epilogue constants ec and log2
 // of its parameter-only prefactor; false outside the factor's domain.
 static __device__ __forceinline__ bool factor_constants(const FactorPlan& F, const double* __restrict__ th,
                                                         const double* tr, const KOut& k, double* ec,
-                                                        double* lnorm2) {
+                                                        double* lnorm2, bool mixed) {
   *lnorm2 = 0.0;
   switch (F.kind) {
-    case FK_GAUSS: return gauss_constants(F, th, tr, k, ec, lnorm2);
+    case FK_GAUSS: return gauss_constants(F, th, tr, k, ec, lnorm2, mixed);
     case FK_EXP: return exp_constants(F, th, tr, k, ec, lnorm2);
-    case FK_CHEB: return cheb_constants(F, th, k, ec);
-    case FK_PWAVE: pwave_constants(F, th, k, ec); return true;
+    case FK_CHEB: return cheb_constants(F, th, k, ec, lnorm2);
+    case FK_PWAVE: pwave_constants(F, th, k, ec, lnorm2); return true;
   }
   return false;
 }
@@ -313,7 +362,7 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
   if (kind2 >= 0 && prologue_wave(kind2, nw) == w) {
     const FactorPlan& F = P.fac[lane];
     const KOut ko{cb->d + F.cst, cb->f + F.cst};
-    ok = factor_constants(F, th, s_tr[lane], ko, cb->e + F.ecst, &s_ln2[lane]) && ok;
+    ok = factor_constants(F, th, s_tr[lane], ko, cb->e + F.ecst, &s_ln2[lane], P.precision == UML_MIXED) && ok;
   }
   if (w == nw - 1 && lane >= 32 && lane - 32 < npar) cb->theta[lane - 32] = th_copy;
   const bool wave_bad = __ballot(ok ? 0 : 1) != 0;
@@ -332,8 +381,11 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
     for (int k = 0; k < 8; ++k) lk2 += k < c_nfrac ? v[k] : 0.0;
 #pragma unroll
     for (int j = 0; j < kMaxFacPerComp; ++j) lk2 += j < c_nfac ? v[8 + j] : 0.0;
+    const float hi = float(lk2);
     cb->d[c_lk2] = lk2;
-    cb->f[c_lk2] = float(lk2);
+    cb->d[c_lk2 + 1] = 0.0;
+    cb->f[c_lk2] = hi;
+    cb->f[c_lk2 + 1] = float(lk2 - double(hi));
   }
   if (tid == 0) {
     int bad = 0;

@@ -46,15 +46,24 @@ enum FactorKind { FK_GAUSS = 1, FK_EXP = 2, FK_CHEB = 3, FK_PWAVE = 4 };
 
 // Kernel constants, moments and epilogue constants per factor kind; the
 // compile-time shapes and the host plan builder both use these.
+//   Gaussian     kernel {c0_hi, c1_hi, c1_lo, k2}, epilogue 5
+//   exponential  kernel {c_hi, c_lo}, epilogue 2
+//   Chebyshev    kernel {s_hi, s_lo, t, sgn, sgn c_1 .. sgn c_N}, epilogue 2N
+//   P-wave       kernel the 8 angular coefficients, epilogue 8
+// The "_lo" entries carry the part of an FP64 constant that its FP32 value
+// drops (zero in the FP64 set); see compute_constants.
 __host__ __device__ constexpr int fk_ncst(int kind, int order) {
-  return kind == FK_GAUSS ? 2 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order + 3 : 9;
+  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 2 : kind == FK_CHEB ? order + 4 : 8;
 }
 __host__ __device__ constexpr int fk_nmom(int kind, int order) {
   return kind == FK_GAUSS ? 2 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order : 8;
 }
 __host__ __device__ constexpr int fk_necst(int kind, int order) {
-  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 2 : kind == FK_CHEB ? 2 * order : 8;
+  return kind == FK_GAUSS ? 5 : kind == FK_EXP ? 2 : kind == FK_CHEB ? 2 * order : 8;
 }
+// Kernel constants of a component ahead of its factors' own: log2 K_c as an
+// FP32 pair (hi, lo).
+constexpr int kCompCst = 2;
 __host__ __device__ constexpr bool fk_expo(int kind) {
   return kind == FK_GAUSS || kind == FK_EXP;
 }
@@ -78,7 +87,7 @@ struct CompPlan {
   int frac_par[8];          // SUM fraction parameters on the path
   int frac_sign[8];         // +1: f, -1: 1 - f
   int frac_ec[8];           // epilogue constant d ln F_c / d f of each entry
-  int cst_lk2;              // offset of log2 K_c
+  int cst_lk2;              // offset of log2 K_c (hi), followed by its lo part
   int slot_r;               // moment slot of r_c
 };
 
