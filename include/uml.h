@@ -196,6 +196,34 @@ int uml_eval_nll_grad(const uml_model* m, const uml_data* d, const double* theta
 int uml_eval_nll_grad_dev(const uml_model* m, const uml_data* d, const double* d_theta_all,
                           double* d_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * evaluation of uml_eval_nll_grad_dev over the caller's own device columns,
+ * with no dataset handle, that allocates nothing.  The event kernel's scratch
+ * memory (its constant cache, completion counters and tile partials) is a
+ * fixed array of UML_NOALLOC_SCRATCH_BYTES in the library's device code, one
+ * per GPU, held until the process ends.
+ *   d_cols   n_dims device pointers (model dimension order), each a column of
+ *            n events in the model's storage type (FP32 for UML_MIXED, FP64
+ *            otherwise), 16-byte aligned; read in place, not copied and not
+ *            range-checked: the caller guarantees every value lies in its
+ *            dimension's range (as uml_data_create would have checked).
+ *   d_w      device weights (same type and alignment) or NULL.
+ *   d_theta_all, d_out  as in uml_eval_nll_grad_dev.
+ * Stream-ordered and asynchronous; results are bitwise equal to
+ * uml_eval_nll_grad_dev on a dataset holding the same events.  The limit:
+ * K * (tiles + 64) * 8 bytes of tile partials, with K the model's moment
+ * count and tiles about n / 4096 (n / 8192 above 2^23 events), must fit in
+ * the array (about 4.5e8 events for the 4-D model); larger n, a model with
+ * precomputed terms, or a null or misaligned pointer give UML_E_INVALID /
+ * UML_E_UNSUPPORTED before anything is queued.  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (different streams or
+ * threads) race and must be serialised by the caller. */
+#define UML_NOALLOC_SCRATCH_BYTES (8u << 20)
+int uml_eval_nll_grad_noalloc(const uml_model* m, int64_t n, const void* const* d_cols,
+                              const void* d_w, const double* d_theta_all, double* d_out,
+                              void* stream);
+
 /* The number of events at which P(x_i | theta) <= 0 or is not finite: the
  * events outside the domain of Eq. 1's logarithm, which make the NLL +inf.
  * Every event counts when theta is outside the model's domain (a fraction

@@ -28,7 +28,7 @@ HIP_FLAGS = ["-mllvm", "-amdgpu-spill-vgpr-to-agpr=0"]
 # parameter count, tile map and job array as five leading arguments preloaded into
 # scalar registers.
 SOURCE_FLAGS = {"eval.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=5"]}
-SOURCES = ["eval.hip", "hess.hip", "gen.hip", "scatter.hip", "model.cpp", "api.cpp", "fit.cpp", "server.cpp"]
+SOURCES = ["eval.hip", "hess.hip", "gen.hip", "scatter.hip", "noalloc.hip", "model.cpp", "api.cpp", "fit.cpp", "server.cpp"]
 
 
 def _compile(src, verbose):

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -156,6 +157,7 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
   J.fit = nullptr;
   J.theta = d->d_theta;
   J.npar = P.npar;
+  J.key = P.key;
 }
 
 // The precomputed event-only terms of a model that stores them (nothing
@@ -355,6 +357,8 @@ int uml_model_create(const uml_model_desc* desc, uml_model** out) {
     delete m;
     return set_error(rc, "uml_model_create: " + err);
   }
+  static std::atomic<long long> serial{0};
+  m->plan.key = ++serial;  // never 0: a cleared constant block matches no model
   const std::string sig = plan_signature(m->plan);
   m->family = find_family(sig);
   if (!m->family) {

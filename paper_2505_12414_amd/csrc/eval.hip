@@ -919,7 +919,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
 #pragma unroll
   for (int d = 0; d < S::ndim; ++d) xref[d] = ((S::shift_mask >> d) & 1u) ? P::xrefs(gc)[d] : T(0);
   const bool eq = lane >= npar || __double_as_longlong(th_l) == __double_as_longlong(gc_l);
-  const bool hit = __all(eq) && gc->valid;  // the same in every wave
+  const bool hit = __all(eq) && gc->valid && gc->key == J.key;  // the same in every wave
   if (!hit) {
     miss_prologue(J.plan, th, npar, red, &s_cb);
 #pragma unroll

@@ -393,6 +393,7 @@ static __device__ __forceinline__ void compute_constants(LdsPlan* P_lds, LdsDoub
     for (int i = 0; i < 16; ++i) bad |= i < nw ? s_bad[i] : 0;
     cb->domain_ok = bad ? 0 : 1;
     cb->valid = 1;
+    cb->key = P.key;
   }
 }
 

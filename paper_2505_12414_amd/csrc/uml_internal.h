@@ -100,6 +100,7 @@ struct EpiTerm {
 constexpr int kMaxTerms = 128;
 
 struct Plan {
+  long long key;  // identifies the model (see ConstBlock::key)
   int ncomp;
   CompPlan comp[kMaxComp];
   int nfac;
@@ -121,7 +122,7 @@ struct Plan {
   int nterm;
   EpiTerm term[kMaxTerms];              // grouped by parameter
   int term_begin[UML_MAX_PARAMS + 1];   // terms of parameter p: [begin[p], begin[p+1])
-  int pad_[3];
+  int pad_[1];
 };
 static_assert(sizeof(Plan) % 16 == 0, "Plan is copied in 16-byte units");
 
@@ -134,8 +135,8 @@ struct ConstBlock {
   double xd[UML_MAX_DIMS];  // per-dimension shifts (FP64)
   float xf[UML_MAX_DIMS];   // the same in FP32 (exact: FP32 values)
   int domain_ok;        // 0 if theta is outside the model's domain
-  int valid;            // 1 once written: theta[] is the key of this block
-  int pad_[2];
+  int valid;            // 1 once written: (key, theta[]) identify this block
+  long long key;        // the model whose plan wrote it (Plan::key)
 };
 static_assert(sizeof(ConstBlock) % 16 == 0, "ConstBlock is copied in 16-byte units");
 
@@ -180,6 +181,7 @@ struct Job {
   FitState* fit;                  // BFGS state (fit mode) or nullptr
   const double* theta;            // parameter vector to evaluate (device)
   int32_t npar;                   // parameters in theta
+  long long key;                  // the model (Plan::key): part of the constant cache's key
 };
 
 // Completion counting: tile t reports to group counter t % kGroups; the last

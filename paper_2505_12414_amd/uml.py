@@ -125,6 +125,7 @@ SIGNATURES = {
     "uml_eval_nll": (C.c_int, [_P, _P, _DP, _DP, _P]),
     "uml_eval_nll_grad": (C.c_int, [_P, _P, _DP, _DP, _DP, _P]),
     "uml_eval_nll_grad_dev": (C.c_int, [_P, _P, _P, _P, _P]),
+    "uml_eval_nll_grad_noalloc": (C.c_int, [_P, C.c_int64, C.POINTER(_P), _P, _P, _P, _P]),
     "uml_eval_hessian": (C.c_int, [_P, _P, _DP, _DP, _DP, _DP, _DP, _P]),
     "uml_eval_bad_events": (C.c_int, [_P, _P, _DP, C.POINTER(C.c_int64), _P]),
     "uml_fit_options_default": (None, [C.POINTER(uml_fit_options)]),
@@ -393,6 +394,22 @@ def uml_eval_nll_grad_dev(model, data, d_theta, d_out, stream=None):
         stream = torch.cuda.current_stream()
     check(lib().uml_eval_nll_grad_dev(model.handle, data.handle, d_theta.data_ptr(),
                                       d_out.data_ptr(), _stream_ptr(stream)))
+
+
+def uml_eval_nll_grad_noalloc(model, n, d_cols, d_w, d_theta, d_out, stream=None):
+    """Stream-ordered, allocation-free: n events in the device columns d_cols
+    (sequence of n_dims CUDA tensors, or raw device addresses), optional
+    weights d_w, d_theta -> d_out as uml_eval_nll_grad_dev."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+
+    def addr(t):
+        return t if isinstance(t, int) else t.data_ptr()
+    cols = (_P * len(d_cols))(*[addr(c) for c in d_cols])
+    check(lib().uml_eval_nll_grad_noalloc(model.handle, int(n), cols,
+                                          None if d_w is None else addr(d_w), addr(d_theta),
+                                          addr(d_out), _stream_ptr(stream)))
 
 
 def uml_eval_hessian(model, data, theta=None, want_w2=False, stream=None, allow_nonpositive=True):
