@@ -473,11 +473,20 @@ __device__ __forceinline__ void load_first_group(const Job& J, int64_t base, Fir
   if (J.w) load_vec<T, VW>(static_cast<const T*>(J.w) + e0, f.w);
 }
 
+// The lane's moment sums are FP64.  FP64: in registers (acc).  Mixed
+// precision: each group of VW events is summed in FP32 and then added to the
+// lane's FP64 sums, which sit in LDS (lds[k * stride], this lane's column of
+// the pass-1 buffer; an LDS FP64 add that returns nothing, so they take no
+// registers).  An FP32 running sum over many events would drop the events
+// whose terms are below half its last place, and responsibilities span many
+// orders of magnitude, so those dropped terms would all have the same sign (a
+// bias that grows with N).
 template <class S, class P, bool W, bool FULL>
 __device__ __forceinline__ void process_tile(const Job& J, int64_t base,
                                              const typename P::T (&c)[S::ncst],
                                              const typename P::T (&xref)[S::ndim],
-                                             typename P::T (&acc)[S::K],
+                                             double (&acc)[kF32<typename P::T> ? 1 : S::K], double* lds,
+                                             int stride,
                                              const FirstGroup<S, P>& first) {
   using T = typename P::T;
   constexpr int VW = P::VW;
@@ -518,9 +527,28 @@ __device__ __forceinline__ void process_tile(const Job& J, int64_t base,
         if constexpr (W) wv[q] = ok ? load_global(wcol + e0 + q) : T(0);
       }
     }
+    if constexpr (kF32<T>) {
+      T a32[S::K];
 #pragma unroll
-    for (int q = 0; q < VW; ++q) {
-      if (FULL || e0 + q < n) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, acc);
+      for (int k = 0; k < S::K; ++k) a32[k] = T(0);
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        if (FULL || e0 + q < n) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, a32);
+      }
+      if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < S::K; ++k) lds[k * stride] = double(a32[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < S::K; ++k)
+          __hip_atomic_fetch_add(lds + k * stride, double(a32[k]), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < VW; ++q) {
+        if (FULL || e0 + q < n) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, acc);
+      }
     }
   }
 }
@@ -848,14 +876,23 @@ __host__ __device__ constexpr int eval_min_waves() {
   return (P::VW == 4 && !S::pre) ? 4 : 1;
 }
 
-// A launch without a tile map evaluates job j0 at the point theta0, with the
-// job's cached constant block cst0 and parameter count npar0.  These lead the
-// argument list, followed by the tile map and the job array; the hardware
-// preloads the five into scalar registers (the library is built that way), so
-// without a tile map the loads of the cache check go out without waiting for
-// the rest of the arguments.  With a tile map each workgroup takes its job's
-// own point, block and count from the job array instead.
-template <class S, class P>
+// Two kernels per model shape and precision:
+//   BATCH = false  one dataset (job j0, tile = workgroup) at the point
+//                  theta0, with the job's cached constant block cst0 and
+//                  parameter count npar0.  These lead the argument list,
+//                  followed by the tile map and the job array; the hardware
+//                  preloads the five into scalar registers (the library is
+//                  built that way), so the loads of the cache check go out
+//                  without waiting for the rest of the arguments, and the
+//                  job's fields stay in scalar registers.
+//   BATCH = true   a ragged launch over many jobs (tile map: workgroup ->
+//                  (job, tile)), each workgroup taking its job's point, block
+//                  and count from the job array; jobs in fit mode take their
+//                  BFGS step in the workgroup that completes them.
+// Keeping the two apart keeps the BFGS step's registers out of the plain
+// evaluation and lets its job descriptor come from the kernel arguments
+// alone.
+template <class S, class P, bool BATCH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min_waves<S, P>()))) void eval_kernel(const double* __restrict__ theta0,
                                                       const ConstBlock* __restrict__ cst0, int npar0,
                                                       const int2* __restrict__ tmap,
@@ -868,7 +905,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   const double* __restrict__ th = theta0;
   const ConstBlock* __restrict__ gc = cst0;
   int npar = npar0;
-  if (tmap) {
+  if constexpr (BATCH) {
     const int2 t = tmap[blockIdx.x];
     jid = t.x;
     tile = t.y;
@@ -882,8 +919,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   // every model has at least one), so nothing waits for them until the check
   const int pl = lane < npar ? lane : 0;
   const double th_l = th[pl], gc_l = gc->theta[pl];
-  const Job J = tmap ? jobs[jid] : j0;
-  if (J.fit && J.fit->done) return;  // a finished fit: its tiles do nothing
+  const Job J = BATCH ? jobs[jid] : j0;
+  if constexpr (BATCH)
+    if (J.fit && J.fit->done) return;  // a finished fit: its tiles do nothing
   __shared__ __align__(16) ConstBlock s_cb;
 
   // Parameter-only constants.  The job keeps the block of the last point it
@@ -906,9 +944,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   // doubles followed by the plan
   constexpr int PASS2_BYTES =
       (K + UML_MAX_PARAMS) * sizeof(double) + sizeof(Plan) + sizeof(ConstBlock) + 16;
-  constexpr int LDS_T = (K * STRIDE * sizeof(T) > PASS2_BYTES) ? K * STRIDE
-                                                               : int(PASS2_BYTES / sizeof(T)) + 4;
-  __shared__ __align__(16) T red[LDS_T];
+  constexpr int LDS_T = (K * STRIDE * sizeof(double) > PASS2_BYTES) ? K * STRIDE
+                                                                    : int(PASS2_BYTES / sizeof(double)) + 4;
+  __shared__ __align__(16) double red[LDS_T];
   __shared__ double red2[K * (PARTS > 16 ? PARTS : 16)];
   __shared__ int s_flag;
 
@@ -929,31 +967,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
       xref[d] = ((S::shift_mask >> d) & 1u) ? to_sgpr(P::xrefs(&s_cb)[d]) : T(0);
   }
 
-  T acc[K];
+  double acc[kF32<T> ? 1 : K];  // FP64: the lane sums; mixed: in LDS (red)
 #pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  for (int k = 0; k < (kF32<T> ? 1 : K); ++k) acc[k] = 0.0;
+  double* lsum = red + tid;
   if (J.w) {
     if (full)
-      process_tile<S, P, true, true>(J, base, c, xref, acc, first);
+      process_tile<S, P, true, true>(J, base, c, xref, acc, lsum, STRIDE, first);
     else
-      process_tile<S, P, true, false>(J, base, c, xref, acc, first);
+      process_tile<S, P, true, false>(J, base, c, xref, acc, lsum, STRIDE, first);
   } else {
     if (full)
-      process_tile<S, P, false, true>(J, base, c, xref, acc, first);
+      process_tile<S, P, false, true>(J, base, c, xref, acc, lsum, STRIDE, first);
     else
-      process_tile<S, P, false, false>(J, base, c, xref, acc, first);
+      process_tile<S, P, false, false>(J, base, c, xref, acc, lsum, STRIDE, first);
   }
 
   // pass 1: lanes -> tile partial, through LDS in a fixed order (buffers
   // declared above)
+  if constexpr (!kF32<T>) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) red[k * STRIDE + tid] = acc[k];
+    for (int k = 0; k < K; ++k) red[k * STRIDE + tid] = acc[k];
+  }
   __syncthreads();
   if (tid < K * PARTS) {
     const int k = tid / PARTS, p = tid % PARTS;
     double s = 0.0;
 #pragma unroll 8
-    for (int i = 0; i < CH; ++i) s += double(red[k * STRIDE + i * PARTS + p]);
+    for (int i = 0; i < CH; ++i) s += red[k * STRIDE + i * PARTS + p];
     red2[k * PARTS + p] = s;
   }
   __syncthreads();
@@ -1010,10 +1051,12 @@ top_level:
   if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
   if (!spare) __syncthreads();
   column_sums<K>(gpart, kGroups, ng, 1, red2, tot);  // ends with a barrier
-  epilogue(*s_plan, hit ? s_gc : &s_cb, tot, (out_override && !tmap) ? out_override : J.out);
-  if (J.fit) {
-    __syncthreads();
-    bfgs_step(*s_plan, J.fit, J.cst, s_gc);  // s_gc is free once the epilogue is done
+  epilogue(*s_plan, hit ? s_gc : &s_cb, tot, (!BATCH && out_override) ? out_override : J.out);
+  if constexpr (BATCH) {
+    if (J.fit) {
+      __syncthreads();
+      bfgs_step(*s_plan, J.fit, J.cst, s_gc);  // s_gc is free once the epilogue is done
+    }
   }
 }
 
@@ -1072,12 +1115,21 @@ void launch_count(const LaunchArgs& a, unsigned long long* d_count) {
 template <class S>
 void launch_eval(const LaunchArgs& a) {
   const double* th0 = a.theta ? a.theta : a.job0.theta;
-  if (a.precision == UML_MIXED)
-    hipLaunchKernelGGL((eval_kernel<S, PrecMixed>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
-                       a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
-  else
-    hipLaunchKernelGGL((eval_kernel<S, PrecF64>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
-                       a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+  if (a.tmap) {
+    if (a.precision == UML_MIXED)
+      hipLaunchKernelGGL((eval_kernel<S, PrecMixed, true>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
+                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+    else
+      hipLaunchKernelGGL((eval_kernel<S, PrecF64, true>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
+                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+  } else {
+    if (a.precision == UML_MIXED)
+      hipLaunchKernelGGL((eval_kernel<S, PrecMixed, false>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
+                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+    else
+      hipLaunchKernelGGL((eval_kernel<S, PrecF64, false>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
+                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+  }
 }
 
 template <class S>

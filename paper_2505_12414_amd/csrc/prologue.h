@@ -247,7 +247,7 @@ static __device__ __forceinline__ void pwave_constants(const FactorPlan& F, cons
     k.put(i, scale[i] * th[F.par[i]]);
     ec[i] = scale[i];
   }
-  *lnorm2 = p_log2(9.0 / (32.0 * M_PI));
+  *lnorm2 = -3.4815711280300066;  // log2(9 / (32 pi))
 }
 
 // Stage 2 for one factor: kernel constants, epilogue constants ec and log2
