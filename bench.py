@@ -113,6 +113,73 @@ def theta_points(torch, model, truth, dev, count=64):
     return [bank[j] for j in range(count)]
 
 
+def time_evals(torch, uml, model, data, points, out, stream, steps, warmup, graph=True):
+    """Microseconds per evaluation of `steps` back-to-back evaluations at the
+    device-resident points in turn (each launch a new point), timed with HIP
+    events on the launch stream.  graph=True: the launches are captured once
+    in a HIP graph and replayed, so the host's per-launch cost does not pace
+    the device; the device work is the same launches."""
+    with torch.cuda.stream(stream):
+        for i in range(warmup):
+            uml.uml_eval_nll_grad_dev(model, data, points[i % len(points)], out, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for i in range(steps):
+                uml.uml_eval_nll_grad_dev(model, data, points[i % len(points)], out, stream=stream)
+        with torch.cuda.stream(stream):
+            g.replay()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            g.replay()
+            ev1.record(stream)
+    else:
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            for i in range(steps):
+                uml.uml_eval_nll_grad_dev(model, data, points[i % len(points)], out, stream=stream)
+            ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) * 1e3 / steps
+
+
+def time_rotated(torch, uml, model, datasets, points, out, stream, steps, graph=True):
+    """As time_evals, with launch i over datasets[i % len(datasets)]."""
+    nd = len(datasets)
+    with torch.cuda.stream(stream):
+        for i in range(2 * nd):
+            uml.uml_eval_nll_grad_dev(model, datasets[i % nd], points[i % len(points)], out, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def issue():
+        for i in range(steps):
+            uml.uml_eval_nll_grad_dev(model, datasets[i % nd], points[i % len(points)], out, stream=stream)
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            issue()
+        with torch.cuda.stream(stream):
+            g.replay()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            g.replay()
+            ev1.record(stream)
+    else:
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            issue()
+            ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) * 1e3 / steps
+
+
 def headline(args, torch, uml, G, W):
     n = args.events
     dtype = np.float32 if args.precision == "mixed" else np.float64
@@ -136,23 +203,14 @@ def headline(args, torch, uml, G, W):
     stream = torch.cuda.Stream(device=dev)
     copy_gbs = copy_check(torch, stream)
 
-    with torch.cuda.stream(stream):
-        for i in range(args.warmup):
-            uml.uml_eval_nll_grad_dev(model, data, points[i % len(points)], out, stream=stream)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    with torch.cuda.stream(stream):
-        ev0.record(stream)
-        for i in range(args.steps):
-            uml.uml_eval_nll_grad_dev(model, data, points[i % len(points)], out, stream=stream)
-        ev1.record(stream)
-    torch.cuda.synchronize()
+    us_step = time_evals(torch, uml, model, data, points, out, stream, args.steps, args.warmup,
+                         graph=not args.no_graph)
     wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)          # HIP events on the kernels' own stream
-    ms_per_step = gpu_ms / args.steps
-    value = n * args.steps / (gpu_ms * 1e-3)
+    ms_per_step = us_step * 1e-3
+    value = n / (ms_per_step * 1e-3)
+    # the same launches issued one by one from the host (no graph)
+    us_eager = time_evals(torch, uml, model, data, points, out, stream, args.steps, 0, graph=False)
 
     esize = 4 if args.precision == "mixed" else 8
     kname = f"eval_kernel ({args.model}, {args.precision}{', precomputed terms' if args.precompute else ''})"
@@ -188,16 +246,8 @@ def headline(args, torch, uml, G, W):
         x2 = G.gen_angmass4d(n2, seed=SEED_DATA + 1, dtype=dtype)
         data2 = uml.Data(model, x2)
         steps2 = max(10, args.steps // 4)
-        with torch.cuda.stream(stream):
-            for i in range(args.warmup):
-                uml.uml_eval_nll_grad_dev(model, data2, points[i % len(points)], out, stream=stream)
-            e2a, e2b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e2a.record(stream)
-            for i in range(steps2):
-                uml.uml_eval_nll_grad_dev(model, data2, points[i % len(points)], out, stream=stream)
-            e2b.record(stream)
-        torch.cuda.synchronize()
-        us2 = e2a.elapsed_time(e2b) / steps2 * 1e3
+        us2 = time_evals(torch, uml, model, data2, points, out, stream, steps2, args.warmup,
+                         graph=not args.no_graph)
         us1 = ms_per_step * 1e3
         per_event_s = (us2 - us1) * 1e-6 / (n2 - n)
         peak = PEAK_FP32_TFLOPS if args.precision == "mixed" else PEAK_FP64_TFLOPS
@@ -215,18 +265,7 @@ def headline(args, torch, uml, G, W):
         ds = [data] + [uml.Data(model, gen(n, seed=SEED_DATA + 100 + r, dtype=dtype))
                        for r in range(args.rotate - 1)]
         steps_c = max(args.rotate * 4, (args.steps // args.rotate) * args.rotate)
-        with torch.cuda.stream(stream):
-            for i in range(args.rotate * 2):
-                uml.uml_eval_nll_grad_dev(model, ds[i % args.rotate], points[i % len(points)], out,
-                                          stream=stream)
-            eca, ecb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            eca.record(stream)
-            for i in range(steps_c):
-                uml.uml_eval_nll_grad_dev(model, ds[i % args.rotate], points[i % len(points)], out,
-                                          stream=stream)
-            ecb.record(stream)
-        torch.cuda.synchronize()
-        us_c = eca.elapsed_time(ecb) / steps_c * 1e3
+        us_c = time_rotated(torch, uml, model, ds, points, out, stream, steps_c, not args.no_graph)
         cold = {"datasets": args.rotate, "working_set_mb": round(args.rotate * n * esize * len(desc["dims"]) / 1e6, 1),
                 "steps": steps_c, "us_per_step": round(us_c, 3)}
         if roofline["bound"] == "hbm":
@@ -247,7 +286,149 @@ def headline(args, torch, uml, G, W):
     roofline["measured_copy_gbs"] = round(copy_gbs, 1)
     return {"desc": desc, "x": x, "truth": truth, "n": n, "model": model, "value": value,
             "ms_per_step": ms_per_step, "wall": wall, "roofline": roofline,
+            "us_per_step_eager": us_eager,
             "nll": float(out[0].item())}
+
+
+# ---------------------------------------------------------------------------
+# Further measurements of the same path: the 4-D model in FP64, the 1-D model
+# (HBM-bound by intent) hot and cold, a 1-D FP64 fit at 1e4 events, and a
+# large weighted 4-D fit with its Hessian (mixed against FP64).
+
+
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def leg_eval(torch, uml, desc, x, precision, truth, steps, warmup, graph, rotate=1, gen=None,
+             seed=SEED_DATA, flop=None):
+    """us per evaluation at a new point per launch, hot (one dataset) and,
+    with rotate > 1, cold (rotate datasets in turn)."""
+    dev = torch.device("cuda:0")
+    model = uml.Model(desc, precision)
+    data = uml.Data(model, x)
+    points = theta_points(torch, model, truth, dev)
+    out = torch.empty(1 + model.n_free, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    n = x.shape[1]
+    esize = 4 if precision == "mixed" else 8
+    us = time_evals(torch, uml, model, data, points, out, stream, steps, warmup, graph)
+    r = {"events": n, "precision": precision, "us_per_step": round(us, 3),
+         "events_per_s": round(n / (us * 1e-6), 1)}
+    if flop is None:   # HBM-bound: the event columns' bytes per evaluation
+        gbs = esize * x.shape[0] * n / (us * 1e-6) / 1e9
+        r.update({"achieved_gbs": round(gbs, 1), "frac_of_hbm": round(gbs / PEAK_HBM_GBS, 4)})
+    else:
+        tf = flop * n / (us * 1e-6) / 1e12
+        peak = PEAK_FP32_TFLOPS if precision == "mixed" else PEAK_FP64_TFLOPS
+        r.update({"achieved_tflops": round(tf, 3), "peak_tflops": peak, "frac": round(tf / peak, 4)})
+        if precision == "mixed":
+            r["frac_of_packed_fp32"] = round(tf / PEAK_FP32_PACKED_TFLOPS, 4)
+    if rotate > 1:
+        dt = np.float32 if precision == "mixed" else np.float64
+        ds = [data] + [uml.Data(model, gen(n, seed=seed + 100 + k, dtype=dt)) for k in range(rotate - 1)]
+        us_c = time_rotated(torch, uml, model, ds, points, out, stream,
+                            max(rotate * 4, (steps // rotate) * rotate), graph)
+        gbs = esize * x.shape[0] * n / (us_c * 1e-6) / 1e9
+        r["cold"] = {"datasets": rotate, "working_set_mb": round(rotate * esize * x.shape[0] * n / 1e6, 1),
+                     "us_per_step": round(us_c, 3), "achieved_gbs": round(gbs, 1),
+                     "frac_of_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+        del ds
+    return r
+
+
+def legs(args, torch, uml, G, W):
+    sel = set(args.legs.split(",")) if args.legs not in ("all", "none") else (
+        set() if args.legs == "none" else {"fp64_4d", "mass1d", "fit1d", "weighted4d"})
+    graph = not args.no_graph
+    steps, warm = max(20, args.steps), max(5, args.warmup)
+    out = {}
+    if "fp64_4d" in sel:
+        x = G.gen_angmass4d(1_000_000, seed=SEED_DATA, dtype=np.float64)
+        out["angmass4d_fp64_1e6"] = leg_eval(torch, uml, W.angmass4d(), x, "fp64",
+                                             W.angmass4d_truth_vector(), steps, warm, graph,
+                                             flop=FLOP_PER_EVENT_4D)
+        print("# leg fp64_4d done", file=sys.stderr, flush=True)
+    if "mass1d" in sel:
+        truth = [5.28, 0.02, -1.5, 0.3]
+        for n in (1_000_000, 10_000_000):
+            for prec in ("mixed", "fp64"):
+                dt = np.float32 if prec == "mixed" else np.float64
+                x = G.gen_mass1d(n, seed=SEED_DATA, dtype=dt)
+                out[f"mass1d_{prec}_{n:.0e}".replace("+0", "")] = leg_eval(
+                    torch, uml, W.mass1d(), x, prec, truth, steps, warm, graph,
+                    rotate=8 if n >= 10_000_000 else 1, gen=G.gen_mass1d)
+        print("# leg mass1d done", file=sys.stderr, flush=True)
+    if "fit1d" in sel:
+        # 1e4 events, FP64 throughout: NLL + gradient, and a BFGS fit from the
+        # start point 5% off truth to EDM < 1e-6 (with its covariance)
+        x = G.gen_mass1d(10_000, seed=SEED_DATA, dtype=np.float64)
+        r = leg_eval(torch, uml, W.mass1d(), x, "fp64", [5.28, 0.02, -1.5, 0.3], steps, warm, graph)
+        model = uml.Model(W.mass1d(), "fp64")
+        data = uml.Data(model, x)
+        start = W.mass1d_start()
+        uml.uml_fit(model, data, start)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            f = uml.uml_fit(model, data, start)
+            ts.append(time.perf_counter() - t0)
+        r.update({"fit_ms": round(1e3 * float(np.median(ts)), 3), "fit_iterations": f["n_iter"],
+                  "fit_evaluations": f["n_eval"], "fit_edm": f["edm"], "fit_status": f["status_name"]})
+        out["mass1d_fp64_1e4"] = r
+        print("# leg fit1d done", file=sys.stderr, flush=True)
+    if "weighted4d" in sel:
+        # 1e7 events drawn on the device, weights U(0.5, 1.5): mixed and FP64
+        # fits with the Hessian covariance, and the Hessian pass alone
+        n = 10_000_000
+        desc = W.angmass4d()
+        mm = uml.Model(desc, "mixed")
+        g = uml.Data.generate(mm, n, SEED_DATA + 7)
+        x = g.download()
+        g.close()
+        w = np.random.default_rng(SEED_DATA + 8).uniform(0.5, 1.5, n).astype(np.float32)
+        truth = np.array(W.angmass4d_truth_vector())
+        res = {}
+        for prec in ("mixed", "fp64"):
+            model = mm if prec == "mixed" else uml.Model(desc, "fp64")
+            xx, ww = (x, w) if prec == "mixed" else (x.astype(np.float64), w.astype(np.float64))
+            data = uml.Data(model, xx, weights=ww)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = uml.uml_fit(model, data, truth)
+            t_fit = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            uml.uml_eval_hessian(model, data, f["theta"])
+            t_h = time.perf_counter() - t0
+            res[prec] = (f, t_fit, t_h)
+            del data
+        fm, f6 = res["mixed"][0], res["fp64"][0]
+        free = np.array([not p.get("fixed", False) for p in desc["params"]])
+        dth = np.abs(fm["theta"][free] - f6["theta"][free]) / f6["errors"][free]
+        dsg = np.abs(fm["errors"][free] - f6["errors"][free]) / f6["errors"][free]
+        out["angmass4d_weighted_1e7"] = {
+            "events": n, "weights": "U(0.5, 1.5)",
+            "fit_ms": {k: round(1e3 * v[1], 2) for k, v in res.items()},
+            "hessian_ms": {k: round(1e3 * v[2], 2) for k, v in res.items()},
+            "fit_iterations": {k: v[0]["n_iter"] for k, v in res.items()},
+            "status": {k: v[0]["status_name"] for k, v in res.items()},
+            "max_dtheta_over_sigma_mixed_vs_fp64": float(dth.max()),
+            "max_rel_dsigma_mixed_vs_fp64": float(dsg.max())}
+        print("# leg weighted4d done", file=sys.stderr, flush=True)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -465,7 +646,7 @@ def cpu_baseline(args, H, S):
         t = time.perf_counter() - t0
     base = {"value": round(k * reps / t, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} events of the benchmark dataset, NLL+gradient, {reps} evaluations "
-                      f"in {t:.1f} s, one thread"}
+                      f"in {t:.1f} s, one thread", "host": host_info()}
     if S is None:
         return base, None
     # the oracle's own fits of the independently generated toys, in order,
@@ -525,6 +706,11 @@ def main():
                     help="second dataset size for the per-event (marginal) rate; 0: skip")
     ap.add_argument("--tight-budget-mb", type=int, default=16,
                     help="budget of a second saturated server run, below the natural footprint; 0: skip")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time launches issued one by one instead of graph replays")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of extra measurements (fp64_4d, mass1d, fit1d, weighted4d) "
+                         "or 'all' or 'none'")
     ap.add_argument("--rotate", type=int, default=1,
                     help="also time the evaluations over this many distinct datasets in turn "
                          "(a working set beyond the last-level cache); 1: skip")
@@ -542,6 +728,7 @@ def main():
     torch.cuda.init()
     H = headline(args, torch, uml, G, W)
     print(f"# headline done: {H['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+    L = legs(args, torch, uml, G, W)
     S = None
     if args.serving_fits > 0:
         S = serving(args, uml, G, W)
@@ -565,7 +752,11 @@ def main():
            "config": {"workload": f"{wl}, {H['n']} events, {prec}", "events": H["n"],
                       "free_params": H["model"].n_free, "precision": args.precision},
            "roofline": H["roofline"], "cpu_baseline": cpu,
-           "nll": H["nll"], "wall_s": round(H["wall"], 4)}
+           "nll": H["nll"], "wall_s": round(H["wall"], 4),
+           "timing": "graph replay of the steps" if not args.no_graph else "launches issued one by one",
+           "us_per_step_eager": round(H["us_per_step_eager"], 3), "host": host_info()}
+    if L:
+        rec["legs"] = L
     if S is not None:
         rec["serving"] = S["record"]
         if cpu_fits is not None:
