@@ -200,7 +200,7 @@ int uml_eval_nll_grad_dev(const uml_model* m, const uml_data* d, const double* d
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * evaluation of uml_eval_nll_grad_dev over the caller's own device columns,
  * with no dataset handle, that allocates nothing.  The event kernel's scratch
- * memory (its constant cache, completion counters and tile partials) is a
+ * memory (its constant cache and tile partials) is a
  * fixed array of UML_NOALLOC_SCRATCH_BYTES in the library's device code, one
  * per GPU, held until the process ends.
  *   d_cols   n_dims device pointers (model dimension order), each a column of
@@ -212,9 +212,9 @@ int uml_eval_nll_grad_dev(const uml_model* m, const uml_data* d, const double* d
  *   d_theta_all, d_out  as in uml_eval_nll_grad_dev.
  * Stream-ordered and asynchronous; results are bitwise equal to
  * uml_eval_nll_grad_dev on a dataset holding the same events.  The limit:
- * K * (tiles + 64) * 8 bytes of tile partials, with K the model's moment
- * count and tiles about n / 4096 (n / 8192 above 2^23 events), must fit in
- * the array (about 4.5e8 events for the 4-D model); larger n, a model with
+ * 2 * K * tiles * 8 bytes of tile partials, with K the model's moment count
+ * and tiles about n / 4096 (n / 8192 above 2^23 events), must fit in the
+ * array (about 2e8 events for the 4-D model); larger n, a model with
  * precomputed terms, or a null or misaligned pointer give UML_E_INVALID /
  * UML_E_UNSUPPORTED before anything is queued.  Every call on a GPU shares
  * that GPU's array: calls that overlap on one GPU (different streams or

@@ -116,8 +116,10 @@ DataLayout data_layout(const Plan& P, int64_t n, bool weighted) {
   L.o_out = align_up(L.o_theta + sizeof(double) * UML_MAX_PARAMS, 256);
   L.o_cnt = align_up(L.o_out + sizeof(double) * (1 + UML_MAX_PARAMS), 256);
   L.o_bad = align_up(L.o_cnt + sizeof(unsigned) * kCounterWords, 256);
-  L.o_part = align_up(L.o_bad + sizeof(unsigned long long), 256);
-  L.bytes_work = L.o_part + sizeof(double) * P.K * (L.n_tiles + kGroups);
+  L.o_epoch = align_up(L.o_bad + sizeof(unsigned long long), 256);
+  L.o_part = align_up(L.o_epoch + sizeof(unsigned long long), 256);
+  L.o_spart = align_up(L.o_part + sizeof(double) * P.K * (L.n_tiles + kGroups), 256);
+  L.bytes_work = L.o_spart + 2 * sizeof(double) * P.K * L.n_tiles;
   return L;
 }
 
@@ -151,6 +153,8 @@ void data_bind(uml_data* d, const uml_model* m, int64_t n, bool weighted, const 
   J.events_per_thread = L.E;
   J.cst = reinterpret_cast<ConstBlock*>(wbase + L.o_cst);
   J.partials = reinterpret_cast<double*>(wbase + L.o_part);
+  J.spart = reinterpret_cast<double*>(wbase + L.o_spart);
+  J.epoch = reinterpret_cast<unsigned long long*>(wbase + L.o_epoch);
   J.counter = reinterpret_cast<unsigned int*>(wbase + L.o_cnt);
   J.out = d->d_out;
   J.plan = m->d_plan;
@@ -180,6 +184,10 @@ hipError_t data_init_work(uml_data* d, const DataLayout& L, hipStream_t s) {
   hipError_t e = data_precompute(d, s);
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(d->d_work, 0, L.o_part, s);
+  if (e == hipSuccess) {
+    launch_fill_sentinel(d->job.spart, 2 * int64_t(d->model->plan.K) * L.n_tiles, s);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(d->d_job, &d->job, sizeof(Job), hipMemcpyHostToDevice, s);
   return e;
 }

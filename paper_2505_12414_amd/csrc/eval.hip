@@ -190,6 +190,26 @@ __device__ __forceinline__ void pwave_terms(T cl, T ck, T ph, T& u0, T (&m)[8]) 
   m[7] = skl2 * (sp * cp);               // S9 / 2
 }
 
+// v = u0 + sum_k c_k m_k with the coefficients c (8 hi parts, then in FP32
+// their 8 lo parts): the lo terms first, then the hi terms, then u0.
+template <class T>
+__device__ __forceinline__ T pwave_value(const T* c, T u0, const T* m) {
+  T val;
+  if constexpr (kF32<T>) {
+    val = c[8] * m[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) val = fma(c[8 + k], m[k], val);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) val = fma(c[k], m[k], val);
+    val += u0;
+  } else {
+    val = u0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) val = fma(c[k], m[k], val);
+  }
+  return val;
+}
+
 // P-wave angular density (Eq. 4) in dimensions (cos theta_l, cos theta_K, phi),
 // without its factor 9/(32 pi) (in the component's prefactor).
 // Written as  v = u0 + c0 (u1 - u0) + sum_k c_k b_k  with
@@ -197,7 +217,10 @@ __device__ __forceinline__ void pwave_terms(T cl, T ck, T ph, T& u0, T (&m)[8]) 
 //   u1 = cos^2 K (1 - cos 2l) = 2 cos^2 K sin^2 l,
 //   b  = the S3, S4, S5, AFB, S7, S8, S9 terms without their constant
 //        factors (1, 4, 2, 4/3, 2, 4, 2), which the prologue folds into
-//        c = {FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8, 2 S9};
+//        c = {FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8, 2 S9} (then, in FP32,
+//        the lo parts of the same 8: their sum over the terms is taken first,
+//        then the hi terms, then u0, so each enters before a rounding of a
+//        value that varies from event to event);
 // moments m = {u1 - u0, b_S3, .., b_S9}.  sin K sin l = sqrt(sin^2 K sin^2 l)
 // needs one square root; 1 - c^2 is one FMA (correctly rounded).
 template <int D0, int D1, int D2>
@@ -215,13 +238,9 @@ struct PWave {
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
     T u0, mm[8];
     pwave_terms(xs[D0], xs[D1], xs[D2], u0, mm);
-    T val = u0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      m[k] = mm[k];
-      val = fma(c[k], mm[k], val);
-    }
-    v = val;
+    for (int k = 0; k < 8; ++k) m[k] = mm[k];
+    v = pwave_value(c, u0, mm);
     (void)e;
   }
 };
@@ -240,13 +259,9 @@ struct PWavePre {
   static std::string sig() { return "Q" + std::to_string(B); }
   template <class T>
   __device__ static __forceinline__ void eval(const T* xs, const T* c, T& e, T& v, T* m) {
-    T val = xs[B];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      m[k] = xs[B + 1 + k];
-      val = fma(c[k], m[k], val);
-    }
-    v = val;
+    for (int k = 0; k < 8; ++k) m[k] = xs[B + 1 + k];
+    v = pwave_value(c, xs[B], m);
     (void)e;
   }
 };
@@ -560,8 +575,9 @@ __device__ __forceinline__ void process_tile(const Job& J, int64_t base,
 // NLL and gradient from the K moment sums: the chain rule through the
 // mixture reduces to d NLL / d theta_p = -sum over p's terms of
 // e[ec] * M[mom] (EpiTerm), one thread per free parameter.
-__device__ __forceinline__ void epilogue(const Plan& P, const ConstBlock* cb,
-                                         const double* __restrict__ tot, double* __restrict__ out) {
+template <class PV, class CV>
+__device__ __forceinline__ void epilogue(const PV& P, const CV* cb, const double* __restrict__ tot,
+                                         double* __restrict__ out) {
   const int tid = threadIdx.x;
   const double nll = -0.69314718055994530942 * tot[0];  // slot 0 holds sum w log2 P
   const bool bad = !cb->domain_ok || !isfinite(nll);
@@ -574,6 +590,16 @@ __device__ __forceinline__ void epilogue(const Plan& P, const ConstBlock* cb,
     out[1 + tid] = bad ? 0.0 : g;
   }
 }
+
+// What the epilogue reads of the plan and of the point's constants, in one
+// small block (LDS of the collecting workgroup).
+struct EpiView {
+  int nfree, domain_ok;
+  int free_idx[UML_MAX_PARAMS];
+  int term_begin[UML_MAX_PARAMS + 1];
+  EpiTerm term[kMaxTerms];
+  double e[kMaxECst];
+};
 
 // Bulk copy of n bytes (a multiple of 16, both 16-byte aligned) by
 // `threads` threads, this one being number `t`: every load is issued before
@@ -846,6 +872,15 @@ __device__ __forceinline__ bool arrive(unsigned* cnt, unsigned members) {
   return last;
 }
 
+// Rounds a collecting workgroup waits for one tile's partials before it gives
+// up (each round is at least one memory round trip: seconds in all).
+constexpr int kSpinLimit = 1 << 22;
+#ifndef UML_POLL_BATCH
+#define UML_POLL_BATCH 1
+#endif
+// Tiles a collecting thread polls at once.
+constexpr int kPollBatch = UML_POLL_BATCH;
+
 template <int K>
 __host__ __device__ constexpr int reduce_parts() {
   int p = 1;
@@ -922,6 +957,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   const Job J = BATCH ? jobs[jid] : j0;
   if constexpr (BATCH)
     if (J.fit && J.fit->done) return;  // a finished fit: its tiles do nothing
+  // single dataset: the launch count, which picks this launch's partial slots
+  unsigned long long epoch = 0;
+  if constexpr (!BATCH) epoch = __hip_atomic_load(J.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __shared__ __align__(16) ConstBlock s_cb;
 
   // Parameter-only constants.  The job keeps the block of the last point it
@@ -999,60 +1037,172 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   }
   __syncthreads();
   const int nt = J.n_tiles;
-  double* gpart = J.partials + int64_t(K) * nt;  // [K][kGroups]
-  // With at most kGroups tiles each tile is its own group: its partial goes
-  // straight to the group partials and the group level is skipped.
-  const bool single = nt <= kGroups;
-  if (tid < K) {
-    double s = 0.0;
-#pragma unroll
-    for (int p = 0; p < PARTS; ++p) s += red2[tid * PARTS + p];
-    // device-coherent store: written through to the point where every XCD's
-    // loads of the same address meet, so no L2 write-back is needed
-    double* dst = single ? gpart + int64_t(tid) * kGroups + tile : J.partials + int64_t(tid) * nt + tile;
-    __hip_atomic_store(dst, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  // Completion, in two levels (see kGroups), each a release/acquire counter
-  // step (arrive) after a barrier that orders this workgroup's stores.
-  const int ng = nt < kGroups ? nt : kGroups;
-  const int g = tile % ng;
   double* tot = reinterpret_cast<double*>(red);
-  __syncthreads();
-  if (single) goto top_level;
-  if (tid == 0)
-    s_flag = arrive(J.counter + g * kCounterStride, unsigned((nt - 1 - g) / ng + 1)) ? 1 : 0;
-  __syncthreads();
-  if (!s_flag) return;
-  // the last tile of group g sums the group's tiles g, g + ng, .. in order
-  {
-    const int members = (nt - 1 - g) / ng + 1;
-    column_sums<K>(J.partials + g, nt, members, ng, red2, tot);
-  }
-  if (tid < K)
-    __hip_atomic_store(gpart + int64_t(tid) * kGroups + g, tot[tid], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-top_level:
-  if (tid == 0) s_flag = arrive(J.counter + kGroups * kCounterStride, unsigned(ng)) ? 1 : 0;
-  __syncthreads();
-  if (!s_flag) return;
-  // The last group: the sum over groups, the plan and the constants.  The
-  // threads the column sums leave idle fetch the plan (and the cached
-  // constants) meanwhile, so the three reads cost one round trip.
-  Plan* s_plan = reinterpret_cast<Plan*>(tot + ((K + UML_MAX_PARAMS + 1) & ~1));  // 16-byte aligned
+  // The epilogue's plan and cached constants live in the pass-1 buffer, after
+  // the K + UML_MAX_PARAMS moment sums (16-byte aligned).
+  Plan* s_plan = reinterpret_cast<Plan*>(tot + ((K + UML_MAX_PARAMS + 1) & ~1));
   ConstBlock* s_gc = reinterpret_cast<ConstBlock*>(reinterpret_cast<char*>(s_plan) + sizeof(Plan));
-  constexpr int QS = K * column_q<K>();
-  constexpr bool spare = kBlock - QS >= 64;
-  if (spare ? tid >= QS : true) {
-    const int t = spare ? tid - QS : tid, nt2 = spare ? kBlock - QS : kBlock;
-    bulk_copy16(s_plan, J.plan, int(sizeof(Plan)), t, nt2);
-    if (hit) bulk_copy16(s_gc, gc, int(sizeof(ConstBlock)), t, nt2);
-  }
-  if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
-  if (!spare) __syncthreads();
-  column_sums<K>(gpart, kGroups, ng, 1, red2, tot);  // ends with a barrier
-  epilogue(*s_plan, hit ? s_gc : &s_cb, tot, (!BATCH && out_override) ? out_override : J.out);
-  if constexpr (BATCH) {
+  if constexpr (!BATCH) {
+    // Single dataset: each tile writes its K partials, every one an FP64
+    // value that replaces the sentinel (kSentinel) left in its slot, and is
+    // done; workgroup 0 then collects them.  A slot is read until it holds a
+    // value (agent-scope atomic loads and stores of naturally aligned 64-bit
+    // words: each read returns either the sentinel or the whole value), so
+    // no counter, no ordering between the slots and no cache write-back is
+    // needed.  Two buffers of slots alternate between launches (the launch
+    // count, J.epoch, picks one): the collector first refills the other
+    // buffer with sentinels for the next launch, so those stores overlap its
+    // wait, and the end of this kernel orders them before the next launch.
+    const int64_t kn = int64_t(K) * nt;
+    double* __restrict__ sp = J.spart + (epoch & 1ull) * kn;  // [K][nt]
+    if (tid < K) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < PARTS; ++p) s += red2[tid * PARTS + p];
+      __hip_atomic_store(sp + int64_t(tid) * nt + tile, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tile != 0) return;
+    {
+      double* nxt = J.spart + ((epoch + 1ull) & 1ull) * kn;
+      const double sentinel = __longlong_as_double(static_cast<long long>(kSentinel));
+      for (int64_t i = tid; i < kn; i += kBlock)
+        __hip_atomic_store(nxt + i, sentinel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the epilogue's share of the plan and of the constants, read while the
+    // partials are polled
+    __shared__ EpiView s_epi;
+    {
+      const Plan* __restrict__ gp = J.plan;
+      const ConstBlock* cbs = hit ? gc : &s_cb;
+      if (tid < UML_MAX_PARAMS) s_epi.free_idx[tid] = gp->free_idx[tid];
+      if (tid <= UML_MAX_PARAMS) s_epi.term_begin[tid] = gp->term_begin[tid];
+      if (tid < kMaxTerms) s_epi.term[tid] = gp->term[tid];
+      if (tid < kMaxECst) s_epi.e[tid] = cbs->e[tid];
+      if (tid == 0) {
+        s_epi.nfree = gp->nfree;
+        s_epi.domain_ok = cbs->domain_ok;
+      }
+    }
+    // thread t sums the tiles t, t + 256, .. in order (Neumaier), polling PB
+    // of them at a time; a wait that exceeds kSpinLimit rounds (seconds)
+    // gives up and the result is NaN
+    constexpr int PB = kPollBatch;
+    double sum[K], cmp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) sum[k] = cmp[k] = 0.0;
+    bool lost = false;
+    for (int t0 = tid; t0 < nt; t0 += PB * kBlock) {
+      double v[PB][K];
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          const int t = t0 + b * kBlock;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            // moment k of tile t at sp[k * nt + t]: a wave's loads are contiguous
+            v[b][k] = t < nt ? __hip_atomic_load(sp + int64_t(k) * nt + t, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : 0.0;
+            ready = ready && static_cast<unsigned long long>(__double_as_longlong(v[b][k])) != kSentinel;
+          }
+        }
+        if (ready) break;
+        if (spin >= kSpinLimit) {
+          lost = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        if (t0 + b * kBlock < nt) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double x = v[b][k], u = sum[k] + x;
+            cmp[k] += fabs(sum[k]) >= fabs(x) ? (sum[k] - u) + x : (x - u) + sum[k];
+            sum[k] = u;
+          }
+        }
+      }
+    }
+    // the 256 thread sums of each moment through LDS in the fixed order of
+    // pass 1
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * STRIDE + tid] = sum[k] + cmp[k];
+    const bool any_lost = __syncthreads_or(lost ? 1 : 0) != 0;
+    if (tid < K * PARTS) {
+      const int k = tid / PARTS, p = tid % PARTS;
+      double x = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < CH; ++i) x += red[k * STRIDE + i * PARTS + p];
+      red2[k * PARTS + p] = x;
+    }
+    __syncthreads();
+    if (tid < K) {
+      double x = 0.0;
+#pragma unroll
+      for (int p = 0; p < PARTS; ++p) x += red2[tid * PARTS + p];
+      tot[tid] = any_lost ? NAN : x;
+    }
+    if (tid == 0) __hip_atomic_store(J.epoch, epoch + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the new point's constants, for the cache: written only now that every
+    // tile has passed its own cache check (a workgroup that started later
+    // could otherwise match the new point against a partly written block)
+    if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
+    __syncthreads();
+    epilogue(s_epi, &s_epi, tot, out_override ? out_override : J.out);
+  } else {
+    double* gpart = J.partials + int64_t(K) * nt;  // [K][kGroups]
+    // With at most kGroups tiles each tile is its own group: its partial goes
+    // straight to the group partials and the group level is skipped.
+    const bool single = nt <= kGroups;
+    if (tid < K) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = 0; p < PARTS; ++p) s += red2[tid * PARTS + p];
+      // device-coherent store: written through to the point where every XCD's
+      // loads of the same address meet, so no L2 write-back is needed
+      double* dst = single ? gpart + int64_t(tid) * kGroups + tile : J.partials + int64_t(tid) * nt + tile;
+      __hip_atomic_store(dst, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // Completion, in two levels (see kGroups), each a release/acquire counter
+    // step (arrive) after a barrier that orders this workgroup's stores.
+    const int ng = nt < kGroups ? nt : kGroups;
+    const int g = tile % ng;
+    __syncthreads();
+    if (!single) {
+      if (tid == 0)
+        s_flag = arrive(J.counter + g * kCounterStride, unsigned((nt - 1 - g) / ng + 1)) ? 1 : 0;
+      __syncthreads();
+      if (!s_flag) return;
+      // the last tile of group g sums the group's tiles g, g + ng, .. in order
+      {
+        const int members = (nt - 1 - g) / ng + 1;
+        column_sums<K>(J.partials + g, nt, members, ng, red2, tot);
+      }
+      if (tid < K)
+        __hip_atomic_store(gpart + int64_t(tid) * kGroups + g, tot[tid], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+    }
+    if (tid == 0) s_flag = arrive(J.counter + kGroups * kCounterStride, unsigned(ng)) ? 1 : 0;
+    __syncthreads();
+    if (!s_flag) return;
+    // The last group: the sum over groups, the plan and the constants.  The
+    // threads the column sums leave idle fetch the plan (and the cached
+    // constants) meanwhile, so the three reads cost one round trip.
+    constexpr int QS = K * column_q<K>();
+    constexpr bool spare = kBlock - QS >= 64;
+    if (spare ? tid >= QS : true) {
+      const int t = spare ? tid - QS : tid, nt2 = spare ? kBlock - QS : kBlock;
+      bulk_copy16(s_plan, J.plan, int(sizeof(Plan)), t, nt2);
+      if (hit) bulk_copy16(s_gc, gc, int(sizeof(ConstBlock)), t, nt2);
+    }
+    if (!hit) bulk_copy16(J.cst, &s_cb, int(sizeof(ConstBlock)));
+    if (!spare) __syncthreads();
+    column_sums<K>(gpart, kGroups, ng, 1, red2, tot);  // ends with a barrier
+    epilogue(*s_plan, hit ? s_gc : &s_cb, tot, J.out);
     if (J.fit) {
       __syncthreads();
       bfgs_step(*s_plan, J.fit, J.cst, s_gc);  // s_gc is free once the epilogue is done
@@ -1177,6 +1327,16 @@ __global__ __launch_bounds__(kBlock) void pwave_terms_kernel(const PrecomputeArg
   static_cast<T*>(a.out[0])[i] = u0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) static_cast<T*>(a.out[1 + k])[i] = m[k];
+}
+
+__global__ __launch_bounds__(kBlock) void fill_sentinel_kernel(double* p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = __longlong_as_double(static_cast<long long>(kSentinel));
+}
+
+void launch_fill_sentinel(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_sentinel_kernel, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, p, n);
 }
 
 void launch_pwave_terms(const PrecomputeArgs& a, int precision, hipStream_t s) {

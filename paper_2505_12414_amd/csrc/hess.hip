@@ -210,8 +210,11 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           m[5] = w * sp;
           m[6] = wc * sp;
           m[7] = skl2 * (sp * cp);
-          T val = u0;
+          T val = T(0);  // the coefficients' lo parts first (zero in FP64), then hi, then u0
+          if constexpr (kHessF32<T>)
+            for (int kk = 0; kk < 8; ++kk) val = fma(kc[8 + kk], m[kk], val);
           for (int kk = 0; kk < 8; ++kk) val = fma(kc[kk], m[kk], val);
+          val += u0;
           v *= val;
           const T iv = T(1) / val;
           for (int kk = 0; kk < 8; ++kk) {

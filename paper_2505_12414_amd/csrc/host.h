@@ -67,7 +67,7 @@ struct DataLayout {
   int E, n_tiles;
   int64_t stride;
   size_t bytes_events, bytes_work;
-  size_t o_job, o_cst, o_theta, o_out, o_cnt, o_bad, o_part;
+  size_t o_job, o_cst, o_theta, o_out, o_cnt, o_bad, o_epoch, o_part, o_spart;
 };
 int convert_events(const Plan& P, int64_t n, const void* const* cols, int32_t dtype, const void* w,
                    std::vector<char>& host, const char* fn);

@@ -28,6 +28,8 @@ struct PrecomputeArgs {
   int64_t n;
 };
 void launch_pwave_terms(const PrecomputeArgs& a, int precision, hipStream_t s);
+// Fills n 64-bit words at p with the tile-partial sentinel (kSentinel).
+void launch_fill_sentinel(double* p, int64_t n, hipStream_t s);
 
 struct Family {
   std::string sig;

@@ -1,6 +1,6 @@
 // The allocation-free evaluation entry point: NLL and gradient over the
 // caller's device columns, with the launch's scratch memory (the constant
-// cache, the completion counters and the tile partials of the event kernel)
+// cache and the tile partials of the event kernel)
 // in a fixed-size array of this library's device code instead of a
 // dataset's work area.
 #include <hip/hip_runtime.h>
@@ -18,10 +18,12 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t up256(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// scratch layout: constant cache | completion counters | tile partials
+// scratch layout: constant cache | launch count | tile partials (the
+// single-dataset event kernel's two alternating buffers of K per tile, each
+// slot the sentinel until written)
 constexpr size_t kScrCst = 0;
-constexpr size_t kScrCnt = up256(kScrCst + sizeof(ConstBlock));
-constexpr size_t kScrPart = up256(kScrCnt + sizeof(unsigned) * kCounterWords);
+constexpr size_t kScrEpoch = up256(kScrCst + sizeof(ConstBlock));
+constexpr size_t kScrPart = up256(kScrEpoch + sizeof(unsigned long long));
 constexpr size_t kScrPartDoubles = (size_t(UML_NOALLOC_SCRATCH_BYTES) - kScrPart) / sizeof(double);
 static_assert(UML_NOALLOC_SCRATCH_BYTES % kAlign == 0 && kScrPart < UML_NOALLOC_SCRATCH_BYTES,
               "scratch layout");
@@ -34,6 +36,10 @@ __device__ __align__(256) unsigned char scratch[UML_NOALLOC_SCRATCH_BYTES];
 constexpr int kMaxDevices = 64;
 std::mutex g_mu;
 unsigned char* g_scratch[kMaxDevices] = {};
+// per device: the extent (K * tiles) of the last call's buffers; a call of
+// another extent refills both buffers first, since each call restores only
+// the slots of its own layout
+int64_t g_extent[kMaxDevices] = {};
 
 __global__ void clear_words(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,10 +48,12 @@ __global__ void clear_words(unsigned* p, int n) {
 
 // The device address of this device's scratch array, looked up on the first
 // call on the device (with the device current); the constant cache and the
-// counters are cleared once then, on the caller's stream.  Later calls leave
-// the counters at zero themselves (the workgroup that completes a count
-// resets it), and the cache is keyed by model and point.
-int scratch_for_current_device(hipStream_t s, unsigned char** out, const char* fn) {
+// launch count are cleared then.  Every call of a new extent (K * tiles)
+// fills both partial buffers with the sentinel over the larger of the two
+// extents, on the caller's stream; a call of the same extent finds them
+// ready (each launch refills the buffer the next one uses).  The cache is
+// keyed by model and point.
+int scratch_for_current_device(hipStream_t s, int64_t extent, unsigned char** out, const char* fn) {
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return set_error(UML_E_HIP, std::string(fn) + ": hipGetDevice: " + hipGetErrorString(e));
@@ -61,6 +69,14 @@ int scratch_for_current_device(hipStream_t s, unsigned char** out, const char* f
     e = hipGetLastError();
     if (e != hipSuccess) return set_error(UML_E_HIP, std::string(fn) + ": " + hipGetErrorString(e));
     g_scratch[dev] = static_cast<unsigned char*>(p);
+    g_extent[dev] = -1;
+  }
+  if (extent != g_extent[dev]) {
+    const int64_t fill = 2 * (extent > g_extent[dev] ? extent : g_extent[dev]);
+    launch_fill_sentinel(reinterpret_cast<double*>(g_scratch[dev] + kScrPart), fill, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_error(UML_E_HIP, std::string(fn) + ": " + hipGetErrorString(e));
+    g_extent[dev] = extent;
   }
   *out = g_scratch[dev];
   return UML_OK;
@@ -88,7 +104,7 @@ extern "C" int uml_eval_nll_grad_noalloc(const uml_model* m, int64_t n, const vo
   if (d_w && reinterpret_cast<uintptr_t>(d_w) % 16)
     return set_error(UML_E_INVALID, std::string(fn) + ": the weights must be 16-byte aligned");
   const DataLayout L = data_layout(P, n, d_w != nullptr);
-  const size_t need = size_t(P.K) * size_t(L.n_tiles + kGroups);
+  const size_t need = 2 * size_t(P.K) * size_t(L.n_tiles);
   if (need > kScrPartDoubles)
     return set_error(UML_E_INVALID, std::string(fn) + ": " + std::to_string(n) +
                                         " events need " + std::to_string(need * sizeof(double)) +
@@ -96,7 +112,7 @@ extern "C" int uml_eval_nll_grad_noalloc(const uml_model* m, int64_t n, const vo
                                         std::to_string(kScrPartDoubles * sizeof(double)));
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* base = nullptr;
-  int rc = scratch_for_current_device(s, &base, fn);
+  int rc = scratch_for_current_device(s, int64_t(P.K) * L.n_tiles, &base, fn);
   if (rc) return rc;
   Job J{};
   for (int kd = 0; kd < P.ndim; ++kd) J.col[kd] = n > 0 ? d_cols[P.user_of_dim[kd]] : nullptr;
@@ -105,8 +121,10 @@ extern "C" int uml_eval_nll_grad_noalloc(const uml_model* m, int64_t n, const vo
   J.n_tiles = L.n_tiles;
   J.events_per_thread = L.E;
   J.cst = reinterpret_cast<ConstBlock*>(base + kScrCst);
-  J.counter = reinterpret_cast<unsigned*>(base + kScrCnt);
-  J.partials = reinterpret_cast<double*>(base + kScrPart);
+  J.counter = nullptr;   // the single-dataset kernel counts nothing
+  J.partials = nullptr;
+  J.spart = reinterpret_cast<double*>(base + kScrPart);
+  J.epoch = reinterpret_cast<unsigned long long*>(base + kScrEpoch);
   J.out = d_out;
   J.plan = m->d_plan;
   J.fit = nullptr;

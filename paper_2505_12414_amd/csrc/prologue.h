@@ -238,13 +238,18 @@ static __device__ __forceinline__ bool cheb_constants(const FactorPlan& F, const
 
 // P-wave density (Eq. 4), evaluated without its factor 9/(32 pi), which goes
 // to the prefactor: coefficients {FL, S3, 4 S4, 2 S5, 4/3 AFB, 2 S7, 4 S8,
-// 2 S9}; d ln A / d S_k = s_k b_k / A' with A' the density without 9/(32 pi).
+// 2 S9} as FP32 pairs (the 8 hi parts, then the 8 lo parts: an FP32 F_L alone
+// is off by up to 4e-8, a shift every event shares); d ln A / d S_k =
+// s_k b_k / A' with A' the density without 9/(32 pi).
 static __device__ __forceinline__ void pwave_constants(const FactorPlan& F, const double* __restrict__ th,
                                                        const KOut& k, double* ec, double* lnorm2) {
   const double scale[8] = {1.0, 1.0, 4.0, 2.0, 4.0 / 3.0, 2.0, 4.0, 2.0};
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    k.put(i, scale[i] * th[F.par[i]]);
+    const double c = scale[i] * th[F.par[i]];
+    const float hi = float(c);
+    k.put2(i, c, hi);
+    k.put2(8 + i, 0.0, c - double(hi));
     ec[i] = scale[i];
   }
   *lnorm2 = -3.4815711280300066;  // log2(9 / (32 pi))

@@ -49,11 +49,11 @@ enum FactorKind { FK_GAUSS = 1, FK_EXP = 2, FK_CHEB = 3, FK_PWAVE = 4 };
 //   Gaussian     kernel {c0_hi, c1_hi, c1_lo, k2}, epilogue 5
 //   exponential  kernel {c_hi, c_lo}, epilogue 2
 //   Chebyshev    kernel {s_hi, s_lo, t, sgn, sgn c_1 .. sgn c_N}, epilogue 2N
-//   P-wave       kernel the 8 angular coefficients, epilogue 8
+//   P-wave       kernel the 8 angular coefficients (hi), then their lo parts, epilogue 8
 // The "_lo" entries carry the part of an FP64 constant that its FP32 value
 // drops (zero in the FP64 set); see compute_constants.
 __host__ __device__ constexpr int fk_ncst(int kind, int order) {
-  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 2 : kind == FK_CHEB ? order + 4 : 8;
+  return kind == FK_GAUSS ? 4 : kind == FK_EXP ? 2 : kind == FK_CHEB ? order + 4 : 16;
 }
 __host__ __device__ constexpr int fk_nmom(int kind, int order) {
   return kind == FK_GAUSS ? 2 : kind == FK_EXP ? 1 : kind == FK_CHEB ? order : 8;
@@ -174,6 +174,10 @@ struct Job {
   int32_t events_per_thread;      // E: events per thread per tile
   ConstBlock* cst;                // constants of the last evaluated point (cache)
   double* partials;               // [K][n_tiles] tile partials, then [K][kGroups] group partials
+                                  // (batched launches)
+  double* spart;                  // 2 x [K][n_tiles] tile partials of single-dataset launches
+                                  // (alternating), each kSentinel until written (see eval_kernel)
+  unsigned long long* epoch;      // single-dataset launches so far (picks the buffer)
   unsigned int* counter;          // completion counters: kGroups group counters
                                   // and one global, each on its own 128-byte line
   double* out;                    // [1 + nfree]: nll, gradient
@@ -183,6 +187,10 @@ struct Job {
   int32_t npar;                   // parameters in theta
   long long key;                  // the model (Plan::key): part of the constant cache's key
 };
+
+// The bit pattern of a tile partial not yet written by the current launch: a
+// signalling NaN, which FP64 arithmetic never produces (its NaNs are quiet).
+constexpr unsigned long long kSentinel = 0x7ff4dead0000beefull;
 
 // Completion counting: tile t reports to group counter t % kGroups; the last
 // tile of a group reports to the global counter.  Same-address device-scope
