@@ -201,15 +201,16 @@ constexpr int kCounterStride = 32;  // uints: one counter per 128-byte line
 constexpr int kCounterWords = (kGroups + 1) * kCounterStride;
 
 // Events per thread per tile for a dataset of n events: about 256 tiles
-// (one per CU) for mid-sized datasets, where the fixed cost of the completion
-// chain dominates, with at most 16 events per thread up to 8M events
-// (measured best from 1e6 to 4e6) and 32 beyond.  A pure function of n and
-// the precision, so a dataset is reduced in the same order whatever else
+// (one per CU) for mid-sized datasets, where the fixed cost of a launch
+// dominates, with at most 16 events per thread up to 2M events, 32 up to 16M
+// and 64 beyond (measured best with a new parameter point per launch: 4-D
+// mixed 1e6 / 4e6 events, 1-D mixed 1e6 / 1e7 / 5e7).  A pure function of n
+// and the precision, so a dataset is reduced in the same order whatever else
 // shares the launch.
 inline int events_per_thread(int64_t n, int precision) {
   const int vw = precision == UML_MIXED ? 4 : 2;
   const int64_t per = n / (int64_t(kBlock) * 256);
-  const int cap = n > (int64_t(1) << 23) ? 32 : 16;
+  const int cap = n <= (int64_t(1) << 21) ? 16 : n <= (int64_t(1) << 24) ? 32 : 64;
   int e = vw;
   while (e < per && e < cap) e *= 2;
   return e;
