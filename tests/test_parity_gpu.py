@@ -171,6 +171,10 @@ FULL = [
     ("mass1d", W.mass1d, 1_000_000, "mixed", 50),
     ("mass1d", W.mass1d, 10_000_000, "mixed", 50),
     ("mass1d", W.mass1d, 10_000_000, "fp64", 10),
+    # larger tiles (32 and 64 events per thread) and the sizes where a
+    # coherent per-event error would be largest in units of sigma
+    ("angmass4d", W.angmass4d, 4_000_000, "mixed", 20),
+    ("mass1d", W.mass1d, 50_000_000, "mixed", 20),
 ]
 
 
