@@ -115,13 +115,14 @@ constexpr bool kHessF32 = std::is_same<T, float>::value;
 // not), so each entry of l_c is written once after the zeroing: plain stores,
 // no read-modify-write chains through LDS.
 template <class T>
-__device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& cb,
-                           const double* hc, const HessPlan& H, int64_t i, T* row) {
+__device__ void hess_event(const Plan& P, const ConstBlock& cb, const double* hc, const HessPlan& H,
+                           T* row) {
   const int nf = P.nfree, nc = P.ncomp;
   T* s = row + 2;
   T* r = s + nf;
   T* lv = r + nc;
   T* q = lv + nc * nf;
+  const T* xs = q + H.nq;  // the event's coordinates, staged with the chunk
   for (int k = 0; k < nc * nf; ++k) lv[k] = T(0);
   T E[kMaxComp], V[kMaxComp];
   for (int c = 0; c < nc; ++c) {
@@ -142,7 +143,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
       T* qf = q + H.q_off[fi];
       switch (F.kind) {
         case FK_GAUSS: {
-          const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
+          const T x = xs[F.dim[0]] - T(F.xref);
           const T d = x - kc[0];
           if constexpr (kHessF32<T>) e = fma(d, fma(-kc[2], d, kc[3]), e);
           e = fma(-d * d, kc[1], e);
@@ -160,7 +161,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           break;
         }
         case FK_EXP: {
-          const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
+          const T x = xs[F.dim[0]] - T(F.xref);
           if constexpr (kHessF32<T>) e = fma(x, kc[1], e);
           e = fma(x, kc[0], e);
           const T lx = x + T(ec[1]);
@@ -171,7 +172,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
         }
         case FK_CHEB: {
           const int k = F.order;
-          const T x = ld<T>(A.col[F.dim[0]], i) - T(F.xref);
+          const T x = xs[F.dim[0]] - T(F.xref);
           const T u = kHessF32<T> ? fma(x, kc[0], fma(x, kc[1], kc[2])) : fma(x, kc[0], kc[2]);
           T tj[kMaxCheb + 1];
           tj[0] = T(1);
@@ -193,8 +194,7 @@ __device__ void hess_event(const HessArgs& A, const Plan& P, const ConstBlock& c
           break;
         }
         case FK_PWAVE: {
-          const T cl = ld<T>(A.col[F.dim[0]], i), ck = ld<T>(A.col[F.dim[1]], i),
-                  ph = ld<T>(A.col[F.dim[2]], i);
+          const T cl = xs[F.dim[0]], ck = xs[F.dim[1]], ph = xs[F.dim[2]];
           const T sl2 = fma(-cl, cl, T(1)), sk2 = fma(-ck, ck, T(1));
           const T skl2 = sk2 * sl2, skl = k_sqrt(skl2);
           T sp, cp;
@@ -311,15 +311,24 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
   const int nb = nf > 16 ? 2 : 1;
   const int nvec = 1 + nf + H.nq;
   const int r_off = 2 + nf, l_off = 2 + nf + nc, q_off = 2 + nf + nc + nc * nf;
+  const int x_off = q_off + H.nq, nd = P.ndim;
   // this thread's vector sum: the staged value it weights, and the
   // responsibility it is multiplied by (-1: none)
   int voff = -1, vr = -1;
-  if (tid == 0) {
+  // Each vector sum is split over vrep threads (thread t: sum t % nvec over
+  // every vrep-th event of a chunk, from event t / nvec); the vrep partials
+  // meet in vbuf and are added in a fixed order.
+  __shared__ double vbuf[kBlock];
+  const int vrep = nvec < kBlock ? kBlock / nvec : 1;
+  const int vj = tid % nvec, vk = tid / nvec;
+  const bool vact = vk < vrep;
+  if (!vact) {
+  } else if (vj == 0) {
     voff = 1;
-  } else if (tid <= nf) {
-    voff = 2 + tid - 1;
-  } else if (tid < nvec) {
-    const int k = tid - 1 - nf;
+  } else if (vj <= nf) {
+    voff = 2 + vj - 1;
+  } else {
+    const int k = vj - 1 - nf;
     int fi = 0;  // the factor of entry k: the last with q_off <= k
     while (fi + 1 < P.nfac && H.q_off[fi + 1] <= k) ++fi;
     int comp = 0;
@@ -347,41 +356,40 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
   const int64_t t1 = t0 + A.tile_events < A.n ? t0 + A.tile_events : A.n;
   for (int64_t c0 = t0; c0 < t1; c0 += A.chunk) {
     const int cnt = int((t1 - c0) < A.chunk ? (t1 - c0) : A.chunk);
-    if (tid < cnt) {
-      T* row = stage + int64_t(tid) * V;
-      row[0] = A.w ? ld<T>(A.w, c0 + tid) : T(1);
-      hess_event<T>(A, P, *sC, sh, H, c0 + tid, row);
+    // the chunk's weights and coordinates into the rows, column by column
+    // (every load of the chunk in flight at once, each column's coalesced)
+    for (int k = tid; k < (nd + 1) * cnt; k += kBlock) {
+      const int d = k / cnt, e = k - d * cnt;
+      T* row = stage + int64_t(e) * V;
+      if (d == 0)
+        row[0] = A.w ? ld<T>(A.w, c0 + e) : T(1);
+      else
+        row[x_off + d - 1] = ld<T>(A.col[d - 1], c0 + e);
     }
     __syncthreads();
-    if (tid < nvec) {  // four events per step, four partial sums combined in a fixed order
-      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    if (tid < cnt) hess_event<T>(P, *sC, sh, H, stage + int64_t(tid) * V);
+    __syncthreads();
+    if (vact) {  // two partial sums per thread, combined in a fixed order
+      double p0 = 0.0, p1 = 0.0;
       const int vo = vr >= 0 ? vr : 0;
-      int e = 0;
-#pragma unroll 2
-      for (; e + 4 <= cnt; e += 4) {
+      int e = vk;
+      for (; e + vrep < cnt; e += 2 * vrep) {
         const T* r0 = stage + e * V;
-        const T* r1 = r0 + V;
-        const T* r2 = r1 + V;
-        const T* r3 = r2 + V;
+        const T* r1 = r0 + vrep * V;
         double v0 = double(r0[0]) * double(r0[voff]), v1 = double(r1[0]) * double(r1[voff]);
-        double v2 = double(r2[0]) * double(r2[voff]), v3 = double(r3[0]) * double(r3[voff]);
         if (vr >= 0) {
           v0 *= double(r0[vo]);
           v1 *= double(r1[vo]);
-          v2 *= double(r2[vo]);
-          v3 *= double(r3[vo]);
         }
         p0 += v0;
         p1 += v1;
-        p2 += v2;
-        p3 += v3;
       }
-      for (; e < cnt; ++e) {
+      if (e < cnt) {
         const T* r0 = stage + e * V;
         const double v0 = double(r0[0]) * double(r0[voff]);
         p0 += vr >= 0 ? v0 * double(r0[vo]) : v0;
       }
-      vacc += (p0 + p1) + (p2 + p3);
+      vbuf[tid] = p0 + p1;
     }
     // matrix sums: per step every lane loads the staged values of its event
     // that this wave's products use (at parameters iq and iq + 16)
@@ -418,6 +426,11 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
       }
     }
     __syncthreads();
+    if (tid < nvec) {  // the chunk's partials of sum tid, in replica order
+      double v = 0.0;
+      for (int r = 0; r < vrep; ++r) v += vbuf[r * nvec + tid];
+      vacc += v;
+    }
   }
   // the tile's sums to LDS (over the staging rows): [2 + nc][nf][nf], then the
   // vector sums

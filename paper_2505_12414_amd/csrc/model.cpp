@@ -502,8 +502,10 @@ bool build_hess_plan(const Plan& P, HessPlan& H, std::string& err) {
   return true;
 }
 
+// The staged row of one event: w, log2 P, s, r, l, q, then the event's
+// coordinates (loaded for the whole chunk at once).
 int hess_row_len(const Plan& P, const HessPlan& H) {
-  return 2 + P.nfree + P.ncomp + P.ncomp * P.nfree + H.nq;
+  return 2 + P.nfree + P.ncomp + P.ncomp * P.nfree + H.nq + P.ndim;
 }
 
 std::string plan_describe(const Plan& P) {
