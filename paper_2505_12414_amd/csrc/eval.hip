@@ -386,15 +386,17 @@ __device__ __forceinline__ void combine(const T (&E)[NC], const T (&V)[NC], T (&
 #pragma unroll
     for (int i = 0; i < NC; ++i) ec[i] = k_exp2(E[i] - Emax);
   }
-  sum = T(0);
+  // (the sum starts from the first term: a literal 0 + Sp_0 is an addition the
+  // compiler must keep, for the sign of a zero)
 #pragma unroll
-  for (int i = 0; i < NC; ++i) {
-    Sp[i] = ec[i] * V[i];
-    sum += Sp[i];
-  }
+  for (int i = 0; i < NC; ++i) Sp[i] = ec[i] * V[i];
+  sum = Sp[0];
+#pragma unroll
+  for (int i = 1; i < NC; ++i) sum += Sp[i];
 }
 
-template <class S, class T, bool W>
+// FIRST: the event starts the sums (each acc[k] is set, not added to).
+template <class S, class T, bool W, bool FIRST = false>
 __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S::ncst],
                                       const T (&xref)[S::ndim], T (&acc)[S::K]) {
   constexpr int NC = S::ncomp;
@@ -405,14 +407,26 @@ __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S
   combine<NC, T>(E, V, ec, Emax, Sp, sum);
   const T l2 = Emax + k_log2(sum);  // log2 P
   const T inv = k_rcp(sum);
-  acc[0] += W ? w * l2 : l2;
+  const auto add = [&](int k, T v) {
+    if constexpr (FIRST)
+      acc[k] = v;
+    else
+      acc[k] += v;
+  };
+  const auto add_prod = [&](int k, T a, T b) {
+    if constexpr (FIRST)
+      acc[k] = a * b;
+    else
+      acc[k] = fma(a, b, acc[k]);
+  };
+  add(0, W ? w * l2 : l2);
   sfor<NC>([&](auto Ic) {
     constexpr int ci = Ic;
     using Cc = typename S::template comp<ci>;
     constexpr int mb = S::mom_base(ci);
     const T r = Sp[ci] * inv;
     const T wr = W ? w * r : r;
-    acc[mb] += wr;
+    add(mb, wr);
     const T wq = (W ? w * ec[ci] : ec[ci]) * inv;  // r_c / V_c
     sfor<Cc::nfac>([&](auto If) {
       constexpr int fi = If;
@@ -420,7 +434,7 @@ __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S
       constexpr int o = mb + Cc::mom_off(fi);
       if constexpr (Fc::expo) {
 #pragma unroll
-        for (int k = 0; k < Fc::nmom; ++k) acc[o + k] = fma(wr, mom[o + k], acc[o + k]);
+        for (int k = 0; k < Fc::nmom; ++k) add_prod(o + k, wr, mom[o + k]);
       } else {
         T q = wq;  // r_c / v_f = wq * prod of the component's other polynomial factors
         sfor<Cc::nfac>([&](auto Ig) {
@@ -429,7 +443,7 @@ __device__ __forceinline__ void event(const T (&x)[S::ndim], T w, const T (&c)[S
           if constexpr (gi != fi && !Gc::expo) q *= pv[ci][gi];
         });
 #pragma unroll
-        for (int k = 0; k < Fc::nmom; ++k) acc[o + k] = fma(q, mom[o + k], acc[o + k]);
+        for (int k = 0; k < Fc::nmom; ++k) add_prod(o + k, q, mom[o + k]);
       }
     });
   });
@@ -544,11 +558,17 @@ __device__ __forceinline__ void process_tile(const Job& J, int64_t base,
     }
     if constexpr (kF32<T>) {
       T a32[S::K];
+      if constexpr (FULL) {  // the group's first event starts its sums
+        event<S, T, W, true>(xv[0], W ? wv[0] : T(1), c, xref, a32);
 #pragma unroll
-      for (int k = 0; k < S::K; ++k) a32[k] = T(0);
+        for (int q = 1; q < VW; ++q) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, a32);
+      } else {
 #pragma unroll
-      for (int q = 0; q < VW; ++q) {
-        if (FULL || e0 + q < n) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, a32);
+        for (int k = 0; k < S::K; ++k) a32[k] = T(0);
+#pragma unroll
+        for (int q = 0; q < VW; ++q) {
+          if (e0 + q < n) event<S, T, W>(xv[q], W ? wv[q] : T(1), c, xref, a32);
+        }
       }
       if (g == 0) {
 #pragma unroll
