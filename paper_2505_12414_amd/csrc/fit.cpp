@@ -1,6 +1,8 @@
 // Fitting entry points (device-resident BFGS).
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,21 +47,56 @@ size_t hess_work_bytes(const uml_model* m, int64_t n, int* n_tiles) {
 
 int hess_sums(const uml_model* m) { return 1 + m->plan.nfree + 2 * m->hplan.npairs; }
 
-// Events staged at once by the Hessian pass: as many as LDS allows, up to
-// one per thread (0 if even one event does not fit).
-static int hess_chunk(const uml_model* m) {
+// The device's LDS per workgroup (160 KiB on gfx950; 64 KiB if it cannot be
+// read) and its compute-unit count.
+struct DevShape {
+  size_t lds;
+  int cus;
+};
+static DevShape dev_shape(int device) {
+  static std::mutex mu;
+  static std::map<int, DevShape> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(device);
+  if (it != cache.end()) return it->second;
+  int v = 0, c = 0;
+  DevShape d{64 * 1024, 256};
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && v > 0)
+    d.lds = size_t(v);
+  if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && c > 0)
+    d.cus = c;
+  cache[device] = d;
+  return d;
+}
+
+// Events staged at once by the Hessian pass of a launch of `tiles`
+// workgroups: as many as LDS allows, up to one per thread (0 if even one
+// event does not fit).  With more workgroups than compute units the staging
+// is sized so that two workgroups share a CU (one's matrix sums overlap the
+// other's event evaluation); with fewer, one workgroup takes up to all of a
+// CU's LDS, so more of its threads evaluate events at once.  The sums do not
+// depend on the chunk (every order is per event, and chunks are multiples of
+// the matrix cores' four events), so the choice cannot change a result.
+static int hess_chunk(const uml_model* m, int64_t tiles) {
   const Plan& P = m->plan;
   const int row = hess_row_len(P, m->hplan);
   const int mat = hess_mat_bytes(P, m->hplan);
-  int chunk = kBlock;
-  while (chunk > 1 && hess_lds_bytes(row, chunk, P.precision, mat) > 60 * 1024) chunk /= 2;
-  return hess_lds_bytes(row, chunk, P.precision, mat) > 64 * 1024 ? 0 : chunk;
+  const DevShape D = dev_shape(m->device);
+  const size_t margin = 8 * 1024;  // the kernel's static LDS and more
+  auto fit = [&](size_t cap) {
+    int chunk = kBlock;
+    while (chunk > 1 && hess_lds_bytes(row, chunk, P.precision, mat) > cap) chunk /= 2;
+    return hess_lds_bytes(row, chunk, P.precision, mat) > cap ? 0 : chunk;
+  };
+  const int shared = fit(D.lds / 2 > margin ? D.lds / 2 - margin : 0);
+  if (shared < 4 || tiles > D.cus) return shared;
+  return fit(D.lds - margin);
 }
 
 // Arguments of the Hessian pass of dataset d at the device parameter vector
 // d_theta; its sums go to d_out, or to the dataset's workspace if d_out is
 // null.
-static int hess_job(const uml_model* m, const uml_data* d, const double* d_theta, double* d_out,
+static int hess_job(const uml_model* m, const uml_data* d, const double* d_theta, double* d_out, int chunk,
                     HessJob& J, const char* fn) {
   if (!m || !d || !d_theta) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
   if (d->model != m)
@@ -68,7 +105,6 @@ static int hess_job(const uml_model* m, const uml_data* d, const double* d_theta
     return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": " + m->hess_err);
   const Plan& P = m->plan;
   const HessLayout HL = hess_layout(m, d->n);
-  const int chunk = hess_chunk(m);
   if (!chunk) return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": model too large for the Hessian pass");
   if (!d->d_hwork || d->hess_tiles != HL.n_tiles)
     return set_error(UML_E_INVALID, std::string(fn) + ": missing Hessian workspace");
@@ -102,7 +138,8 @@ int hessian_queue(const uml_model* m, uml_data* d, const double* d_theta, double
                   hipStream_t s, const char* fn) {
   if (!h_out) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
   HessJob J;
-  int rc = hess_job(m, d, d_theta, nullptr, J, fn);
+  if (!m || !d) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+  int rc = hess_job(m, d, d_theta, nullptr, hess_chunk(m, hess_layout(m, d->n).n_tiles), J, fn);
   if (rc != UML_OK) return rc;
   launch_hessian(J.A, d_theta, const_cast<ConstBlock*>(J.A.cb), const_cast<double*>(J.A.hc), J.out,
                  m->plan.precision, s);
@@ -120,9 +157,15 @@ int hessian_queue_batch(const uml_model* m, uml_data* const* ds, const double* c
                         int map_cap, hipStream_t s, const char* fn) {
   if (n <= 0) return UML_OK;
   const int M = hess_sums(m);
+  int64_t tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!ds[i]) return set_error(UML_E_INVALID, std::string(fn) + ": null argument");
+    tiles += hess_layout(m, ds[i]->n).n_tiles;
+  }
+  const int chunk = hess_chunk(m, tiles);
   int n_map = 0;
   for (int i = 0; i < n; ++i) {
-    int rc = hess_job(m, ds[i], d_thetas[i], d_outs + size_t(i) * M, h_jobs[i], fn);
+    int rc = hess_job(m, ds[i], d_thetas[i], d_outs + size_t(i) * M, chunk, h_jobs[i], fn);
     if (rc != UML_OK) return rc;
     for (int t = 0; t < h_jobs[i].A.n_tiles; ++t) {
       if (n_map >= map_cap) return set_error(UML_E_INVALID, std::string(fn) + ": Hessian tile map full");

@@ -266,7 +266,8 @@ typedef double hess_d4 __attribute__((ext_vector_type(4)));
 //   product 0: sum w s s^T,  product 1: sum w^2 s s^T,
 //   product 2 + c: sum w r_c l_c l_c^T (component c),
 // each as 1 or 2 x 2 blocks of 16 x 16 (block b: rows 16 (b >> 1), columns
-// 16 (b & 1)).  Product p belongs to wave p % 4.
+// 16 (b & 1); block 2, below the diagonal, is never formed, since the sums
+// are symmetric).  Product p belongs to wave p % 4.
 static_assert(kBlock == 256, "the Hessian tile assigns its matrix products to four waves");
 constexpr int kHessProdPerWave = (2 + kMaxComp + 3) / 4;
 
@@ -315,9 +316,11 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
   // this thread's vector sum: the staged value it weights, and the
   // responsibility it is multiplied by (-1: none)
   int voff = -1, vr = -1;
-  // Each vector sum is split over vrep threads (thread t: sum t % nvec over
-  // every vrep-th event of a chunk, from event t / nvec); the vrep partials
-  // meet in vbuf and are added in a fixed order.
+  // Each vector sum is split over vrep threads: thread t takes sum t % nvec
+  // over the tile's events t / nvec, t / nvec + vrep, .. in order, in one
+  // running FP64 sum (so the result does not depend on the chunk size); the
+  // vrep partials meet in vbuf at the end of the tile and are added in a
+  // fixed order.
   __shared__ double vbuf[kBlock];
   const int vrep = nvec < kBlock ? kBlock / nvec : 1;
   const int vj = tid % nvec, vk = tid / nvec;
@@ -338,7 +341,7 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
     voff = q_off + k;
     vr = r_off + comp;
   }
-  double vacc = 0.0;
+  double vpart = 0.0;  // this thread's share of its vector sum
   // this wave's products (wave w takes products w and w + 4), each with its
   // nb x nb accumulator blocks; the wave index is made uniform explicitly so
   // the choice of operands is a scalar branch
@@ -369,27 +372,14 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
     __syncthreads();
     if (tid < cnt) hess_event<T>(P, *sC, sh, H, stage + int64_t(tid) * V);
     __syncthreads();
-    if (vact) {  // two partial sums per thread, combined in a fixed order
-      double p0 = 0.0, p1 = 0.0;
+    if (vact) {
       const int vo = vr >= 0 ? vr : 0;
-      int e = vk;
-      for (; e + vrep < cnt; e += 2 * vrep) {
-        const T* r0 = stage + e * V;
-        const T* r1 = r0 + vrep * V;
-        double v0 = double(r0[0]) * double(r0[voff]), v1 = double(r1[0]) * double(r1[voff]);
-        if (vr >= 0) {
-          v0 *= double(r0[vo]);
-          v1 *= double(r1[vo]);
-        }
-        p0 += v0;
-        p1 += v1;
-      }
-      if (e < cnt) {
+      const int lc0 = int(c0 - t0);  // the chunk's first event within the tile
+      for (int e = (vk - lc0 % vrep + vrep) % vrep; e < cnt; e += vrep) {
         const T* r0 = stage + e * V;
         const double v0 = double(r0[0]) * double(r0[voff]);
-        p0 += vr >= 0 ? v0 * double(r0[vo]) : v0;
+        vpart += vr >= 0 ? v0 * double(r0[vo]) : v0;
       }
-      vbuf[tid] = p0 + p1;
     }
     // matrix sums: per step every lane loads the staged values of its event
     // that this wave's products use (at parameters iq and iq + 16)
@@ -418,20 +408,21 @@ __device__ __forceinline__ void hess_tile(const HessArgs& A, int tile) {
           macc[u][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, macc[u][0], 0, 0, 0);
           if (nb == 2) {
             const double a1 = x1 * sc;
+            // block 2 (rows 16-31, columns 0-15) lies below the diagonal: every
+            // pair read at the end has a <= b, so it is not formed
             macc[u][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x1, macc[u][1], 0, 0, 0);
-            macc[u][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x0, macc[u][2], 0, 0, 0);
             macc[u][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, macc[u][3], 0, 0, 0);
           }
         }
       }
     }
     __syncthreads();
-    if (tid < nvec) {  // the chunk's partials of sum tid, in replica order
-      double v = 0.0;
-      for (int r = 0; r < vrep; ++r) v += vbuf[r * nvec + tid];
-      vacc += v;
-    }
   }
+  if (vact) vbuf[tid] = vpart;
+  __syncthreads();
+  double vacc = 0.0;
+  if (tid < nvec)  // the vrep partials of sum tid, in replica order
+    for (int r = 0; r < vrep; ++r) vacc += vbuf[r * nvec + tid];
   // the tile's sums to LDS (over the staging rows): [2 + nc][nf][nf], then the
   // vector sums
   double* mats = reinterpret_cast<double*>(stage);
