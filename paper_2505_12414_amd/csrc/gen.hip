@@ -83,6 +83,27 @@ __device__ double pwave_value(double ctl, double ctk, double phi, const double* 
   return 9.0 / (32.0 * kPi) * v;
 }
 
+// The same bracket in FP32 with the hardware sine and cosine, for a quick
+// accept-reject decision: sin^2 from (1 - c)(1 + c) formed in FP64, so each
+// basis term carries a relative error of a few FP32 ulps and the sine and
+// cosine an absolute one of about 1e-7; the value is within about 2e-6 times
+// the envelope of the FP64 one.
+__device__ float pwave_value_f32(double ctl, double ctk, double phi, const float* c) {
+  const float FL = c[0], S3 = c[1], S4 = c[2], S5 = c[3], AFB = c[4], S7 = c[5], S8 = c[6], S9 = c[7];
+  const float cl = float(ctl), ck = float(ctk);
+  const float sl2 = float(1.0 - ctl) * float(1.0 + ctl), sk2 = float(1.0 - ctk) * float(1.0 + ctk);
+  const float sl = sqrtf(sl2), sk = sqrtf(sk2);
+  const float c2l = 2.0f * cl * cl - 1.0f;
+  const float s2l = 2.0f * sl * cl, s2k = 2.0f * sk * ck;
+  const float ph = float(phi);
+  const float cp = __cosf(ph), sp = __sinf(ph), c2p = __cosf(2.0f * ph), s2p = __sinf(2.0f * ph);
+  const float v = (1.0f - FL) * (0.75f * sk2) + FL * (ck * ck) + (1.0f - FL) * (0.25f * sk2 * c2l) -
+                  FL * (ck * ck * c2l) + S3 * (sk2 * sl2 * c2p) + S4 * (s2k * s2l * cp) +
+                  S5 * (s2k * sl * cp) + AFB * (4.0f / 3.0f * sk2 * cl) + S7 * (s2k * sl * sp) +
+                  S8 * (s2k * s2l * sp) + S9 * (sk2 * sl2 * s2p);
+  return float(9.0 / (32.0 * kPi)) * v;
+}
+
 // Draws the dimensions of one leaf into x (user order); false if the draw
 // hit the attempt cap.
 __device__ bool draw_leaf(const GenPlan& G, const GenNode& nd, const double* th, Stream& s, double* x) {
@@ -141,10 +162,19 @@ __device__ bool draw_leaf(const GenPlan& G, const GenNode& nd, const double* th,
       for (int k = 1; k < 8; ++k)
         if (k != 4) env += fabs(c[k]);
       env *= 9.0 / (32.0 * kPi);
+      // The decision u4 env <= value is taken from the FP32 value when the two
+      // sides differ by more than 1e-4 env (fifty times its error bound), and
+      // from the FP64 value otherwise, so it is always the FP64 decision.
+      float cf[8];
+      for (int k = 0; k < 8; ++k) cf[k] = float(c[k]);
+      const float margin = float(1e-4 * env);
       for (int a = 0; a < kGenCap; ++a) {
         const double u1 = s.next(), u2 = s.next(), u3 = s.next(), u4 = s.next();
         const double ctl = 2.0 * u1 - 1.0, ctk = 2.0 * u2 - 1.0, phi = kPi * (2.0 * u3 - 1.0);
-        if (u4 * env <= pwave_value(ctl, ctk, phi, c)) {
+        const double lhs = u4 * env;
+        const float gap = float(lhs) - pwave_value_f32(ctl, ctk, phi, cf);
+        const bool accept = gap > margin ? false : gap < -margin ? true : lhs <= pwave_value(ctl, ctk, phi, c);
+        if (accept) {
           x[nd.dim[0]] = ctl;
           x[nd.dim[1]] = ctk;
           x[nd.dim[2]] = phi;
