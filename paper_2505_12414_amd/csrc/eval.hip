@@ -933,13 +933,14 @@ __host__ __device__ constexpr int eval_min_waves() {
 
 // Two kernels per model shape and precision:
 //   BATCH = false  one dataset (job j0, tile = workgroup) at the point
-//                  theta0, with the job's cached constant block cst0 and
-//                  parameter count npar0.  These lead the argument list,
-//                  followed by the tile map and the job array; the hardware
-//                  preloads the five into scalar registers (the library is
-//                  built that way), so the loads of the cache check go out
-//                  without waiting for the rest of the arguments, and the
-//                  job's fields stay in scalar registers.
+//                  theta0, with the job's cached constant block cst0, plan
+//                  plan0, model key key0 and parameter count npar0.  These
+//                  lead the argument list; the hardware preloads the five
+//                  into scalar registers (the library is built that way), so
+//                  the loads of the cache check, the check itself and a
+//                  missing point's prologue go ahead without waiting for the
+//                  rest of the arguments, and the job's fields stay in
+//                  scalar registers.
 //   BATCH = true   a ragged launch over many jobs (tile map: workgroup ->
 //                  (job, tile)), each workgroup taking its job's point, block
 //                  and count from the job array; jobs in fit mode take their
@@ -949,7 +950,8 @@ __host__ __device__ constexpr int eval_min_waves() {
 // alone.
 template <class S, class P, bool BATCH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min_waves<S, P>()))) void eval_kernel(const double* __restrict__ theta0,
-                                                      const ConstBlock* __restrict__ cst0, int npar0,
+                                                      const ConstBlock* __restrict__ cst0,
+                                                      const Plan* __restrict__ plan0, long long key0, int npar0,
                                                       const int2* __restrict__ tmap,
                                                       const Job* __restrict__ jobs,
                                                       double* __restrict__ out_override, const Job j0) {
@@ -977,6 +979,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
   const Job J = BATCH ? jobs[jid] : j0;
   if constexpr (BATCH)
     if (J.fit && J.fit->done) return;  // a finished fit: its tiles do nothing
+  const Plan* __restrict__ plan = BATCH ? J.plan : plan0;
+  const long long key = BATCH ? J.key : key0;
   // single dataset: the launch count, which picks this launch's partial slots
   unsigned long long epoch = 0;
   if constexpr (!BATCH) epoch = __hip_atomic_load(J.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1015,9 +1019,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
 #pragma unroll
   for (int d = 0; d < S::ndim; ++d) xref[d] = ((S::shift_mask >> d) & 1u) ? P::xrefs(gc)[d] : T(0);
   const bool eq = lane >= npar || __double_as_longlong(th_l) == __double_as_longlong(gc_l);
-  const bool hit = __all(eq) && gc->valid && gc->key == J.key;  // the same in every wave
+  const bool hit = __all(eq) && gc->valid && gc->key == key;  // the same in every wave
   if (!hit) {
-    miss_prologue(J.plan, th, npar, red, &s_cb);
+    miss_prologue(plan, th, npar, red, &s_cb);
 #pragma unroll
     for (int i = 0; i < S::ncst; ++i) c[i] = to_sgpr(P::consts(&s_cb)[i]);
 #pragma unroll
@@ -1092,7 +1096,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(eval_min
     // partials are polled
     __shared__ EpiView s_epi;
     {
-      const Plan* __restrict__ gp = J.plan;
+      const Plan* __restrict__ gp = plan;
       const ConstBlock* cbs = hit ? gc : &s_cb;
       if (tid < UML_MAX_PARAMS) s_epi.free_idx[tid] = gp->free_idx[tid];
       if (tid <= UML_MAX_PARAMS) s_epi.term_begin[tid] = gp->term_begin[tid];
@@ -1288,17 +1292,17 @@ void launch_eval(const LaunchArgs& a) {
   if (a.tmap) {
     if (a.precision == UML_MIXED)
       hipLaunchKernelGGL((eval_kernel<S, PrecMixed, true>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
-                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+                         a.job0.cst, a.job0.plan, a.job0.key, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
     else
       hipLaunchKernelGGL((eval_kernel<S, PrecF64, true>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
-                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+                         a.job0.cst, a.job0.plan, a.job0.key, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
   } else {
     if (a.precision == UML_MIXED)
       hipLaunchKernelGGL((eval_kernel<S, PrecMixed, false>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
-                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+                         a.job0.cst, a.job0.plan, a.job0.key, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
     else
       hipLaunchKernelGGL((eval_kernel<S, PrecF64, false>), dim3(a.grid), dim3(kBlock), 0, a.stream, th0,
-                         a.job0.cst, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
+                         a.job0.cst, a.job0.plan, a.job0.key, a.job0.npar, a.tmap, a.jobs, a.out, a.job0);
   }
 }
 
