@@ -215,34 +215,40 @@ int unpack_hessian(const uml_model* m, const double* h, double* nll, double* gra
   return UML_OK;
 }
 
-// Inverse of a symmetric positive-definite n x n matrix (row-major) by
-// Cholesky factorisation, in FP64.  Returns false if A is not PD.
+// Inverse of a symmetric positive-definite n x n matrix (row-major, n at
+// most UML_MAX_PARAMS) by Cholesky factorisation, in FP64: A = L L^T, W =
+// L^-1 (lower triangular, by forward substitution), A^-1 = W^T W (formed
+// symmetric).  Each diagonal element of L is divided into once.  Returns
+// false if A is not PD.
 bool chol_inverse(int n, const double* A, double* Ai) {
-  std::vector<double> L(size_t(n) * n, 0.0);
+  double L[UML_MAX_PARAMS * UML_MAX_PARAMS], W[UML_MAX_PARAMS * UML_MAX_PARAMS], id[UML_MAX_PARAMS];
   for (int j = 0; j < n; ++j) {
     double s = A[j * n + j];
     for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
     if (!(s > 0.0) || !std::isfinite(s)) return false;
-    L[j * n + j] = std::sqrt(s);
+    const double d = std::sqrt(s);
+    L[j * n + j] = d;
+    id[j] = 1.0 / d;
     for (int i = j + 1; i < n; ++i) {
       double t = A[i * n + j];
       for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
-      L[i * n + j] = t / L[j * n + j];
+      L[i * n + j] = t * id[j];
     }
   }
-  std::vector<double> y(n);
   for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
-      y[i] = t / L[i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double t = y[i];
-      for (int k = i + 1; k < n; ++k) t -= L[k * n + i] * Ai[k * n + c];
-      Ai[i * n + c] = t / L[i * n + i];
+    W[c * n + c] = id[c];
+    for (int i = c + 1; i < n; ++i) {
+      double t = 0.0;
+      for (int k = c; k < i; ++k) t -= L[i * n + k] * W[k * n + c];
+      W[i * n + c] = t * id[i];
     }
   }
+  for (int a = 0; a < n; ++a)
+    for (int b = a; b < n; ++b) {
+      double t = 0.0;
+      for (int k = b; k < n; ++k) t += W[k * n + a] * W[k * n + b];
+      Ai[a * n + b] = Ai[b * n + a] = t;
+    }
   return true;
 }
 
@@ -250,12 +256,11 @@ bool chol_inverse(int n, const double* A, double* Ai) {
 // (its diagonal inverse if the Hessian is not positive definite there).
 int metric_from_sums(const uml_model* m, const double* h, double* V0, double* nll0, const char* fn) {
   const int nf = m->plan.nfree;
-  std::vector<double> H(size_t(nf) * nf);
-  int rc = unpack_hessian(m, h, nll0, nullptr, H.data(), nullptr, fn);
+  double H[UML_MAX_PARAMS * UML_MAX_PARAMS], Vi[UML_MAX_PARAMS * UML_MAX_PARAMS];
+  int rc = unpack_hessian(m, h, nll0, nullptr, H, nullptr, fn);
   if (rc != UML_OK) return rc;
-  std::vector<double> Vi(size_t(nf) * nf);
   for (int i = 0; i < UML_MAX_PARAMS * UML_MAX_PARAMS; ++i) V0[i] = 0.0;
-  if (chol_inverse(nf, H.data(), Vi.data())) {
+  if (chol_inverse(nf, H, Vi)) {
     for (int i = 0; i < nf; ++i)
       for (int j = 0; j < nf; ++j) V0[i * UML_MAX_PARAMS + j] = Vi[i * nf + j];
   } else {
@@ -299,24 +304,26 @@ void finish_from_sums(const uml_model* m, const double* h, const double* theta,
                       const uml_fit_options& o, uml_fit_result* r, const char* fn) {
   const Plan& P = m->plan;
   const int nf = P.nfree;
-  std::vector<double> g(nf), H(size_t(nf) * nf), C(size_t(nf) * nf, 0.0), W2(size_t(nf) * nf);
+  constexpr int kN2 = UML_MAX_PARAMS * UML_MAX_PARAMS;
+  double g[UML_MAX_PARAMS], H[kN2], C[kN2], W2[kN2], V[kN2];
   double nll = 0.0;
   for (int k = 0; k < UML_MAX_PARAMS; ++k) r->params[k] = k < P.npar ? theta[k] : 0.0;
-  if (unpack_hessian(m, h, &nll, g.data(), H.data(), W2.data(), fn) != UML_OK) {
+  if (unpack_hessian(m, h, &nll, g, H, W2, fn) != UML_OK) {
     r->status = UML_FIT_PDF_NONPOSITIVE;
     r->nll = INFINITY;
     return;
   }
-  if (!chol_inverse(nf, H.data(), C.data())) {
+  if (!chol_inverse(nf, H, C)) {
     if (r->status == UML_FIT_CONVERGED) r->status = UML_FIT_HESSIAN_NOT_PD;
-    std::fill(C.begin(), C.end(), 0.0);
+    for (int i = 0; i < nf * nf; ++i) C[i] = 0.0;
   }
   double edm = 0.0;
   for (int a = 0; a < nf; ++a)
     for (int b = 0; b < nf; ++b) edm += 0.5 * g[a] * C[a * nf + b] * g[b];
-  std::vector<double> V = C;
+  for (int i = 0; i < nf * nf; ++i) V[i] = C[i];
   if (o.cov_kind == UML_COV_SANDWICH) {  // V = C W2 C
-    std::vector<double> T(size_t(nf) * nf, 0.0);
+    double T[kN2];
+    for (int i = 0; i < nf * nf; ++i) T[i] = 0.0;
     for (int a = 0; a < nf; ++a)
       for (int k = 0; k < nf; ++k)
         for (int b = 0; b < nf; ++b) T[a * nf + b] += C[a * nf + k] * W2[k * nf + b];
