@@ -198,10 +198,38 @@ hipError_t data_upload(uml_data* d, const DataLayout& L, const std::vector<char>
   return e;
 }
 
+// Unfolds the subtree at node id into steps of G, with `cont` the step that
+// follows it; returns its entry step, or -2 if the steps exceed the plan.  A
+// product is no step of its own: its children are chained in order, the
+// last one followed by `cont`.  A node under two parents is unfolded once
+// under each.
+static int gen_unfold(GenPlan& G, int id, int cont) {
+  const GenNode& nd = G.node[id];
+  if (nd.kind == UML_PROD) {
+    int c = cont;
+    for (int k = nd.nchild - 1; k >= 0 && c != -2; --k) c = gen_unfold(G, nd.child[k], c);
+    return c;
+  }
+  if (G.nstep >= kMaxGenSteps) return -2;
+  const int s = G.nstep++;
+  G.step[s] = GenStep{nd.kind, id, cont, {-1, -1}};
+  if (nd.kind == UML_SUM) {
+    const int a = gen_unfold(G, nd.child[0], cont);
+    const int b = a == -2 ? -2 : gen_unfold(G, nd.child[1], cont);
+    if (b == -2) return -2;
+    G.step[s].child[0] = a;
+    G.step[s].child[1] = b;
+  }
+  return s;
+}
+
 // Parameters a model can be sampled at: fractions in [0, 1], Gaussian
 // widths > 0, everything finite.
 int check_generation_theta(const uml_model* m, const double* th, const char* fn) {
   const GenPlan& G = m->gplan;
+  if (G.nstep < 0)
+    return set_error(UML_E_UNSUPPORTED, std::string(fn) + ": the model tree unfolds into more than " +
+                                            std::to_string(kMaxGenSteps) + " generation steps");
   for (int k = 0; k < G.npar; ++k)
     if (!std::isfinite(th[k]))
       return set_error(UML_E_INVALID, std::string(fn) + ": parameter " + std::to_string(k) + " is not finite");
@@ -397,6 +425,8 @@ int uml_model_create(const uml_model_desc* desc, uml_model** out) {
     g.nchild = s.n_children;
     for (int k = 0; k < 4; ++k) g.child[k] = s.children[k];
   }
+  G.root_step = gen_unfold(G, G.root, -1);
+  if (G.root_step < 0) G.nstep = -1;
   for (int ud = 0; ud < desc->n_dims; ++ud) {
     G.lo[ud] = desc->dims[ud].lo;
     G.hi[ud] = desc->dims[ud].hi;

@@ -2,20 +2,20 @@
 // events drawn from a model at a parameter point, written straight into a
 // dataset's event columns, so a toy fit needs no upload.
 //
-// Each event is drawn by one thread from its own uniform stream: Philox4x64
-// with 10 rounds (the counter-based generator of Salmon, Moraes, Dror and
-// Shaw, SC11) at counters (b, event, 0, 0), b = 0, 1, .., key (seed, 0); each
-// 64-bit word gives u = (top 53 bits + 1/2) / 2^53.  An event depends only on
-// (seed, index), never on the launch.  The model tree is walked depth first:
-// a sum picks its first child when u < f, a product draws every child in
-// order, and the leaves draw their dimensions:
+// Each event is drawn from its own uniform stream: Philox4x64 with 10 rounds
+// (the counter-based generator of Salmon, Moraes, Dror and Shaw, SC11) at
+// counters (b, event, 0, 0), b = 0, 1, .., key (seed, 0); each 64-bit word
+// gives u = (top 53 bits + 1/2) / 2^53.  An event depends only on (seed,
+// index), never on the launch or the lane that draws it.  The model tree is
+// walked depth first: a sum picks its first child when u < f, a product draws
+// every child in order, and the leaves draw their dimensions:
 //   Gaussian     Box-Muller, rejected outside the range;
 //   exponential  inverse distribution function;
 //   Chebyshev    accept-reject under 1 + sum |c_j|;
 //   P-wave       accept-reject of uniform angles under the sum of the
 //                absolute coefficients times the maxima of their terms.
 // Every accept-reject loop stops after kGenCap attempts (the event is then
-// counted as failed), so every thread finishes.
+// counted as failed), so every lane finishes.
 //
 // Arithmetic is FP64 without contraction of multiplies and adds.
 #include <hip/hip_runtime.h>
@@ -47,29 +47,10 @@ __device__ __forceinline__ void philox4x64(uint64_t x[4], uint64_t k0, uint64_t 
   }
 }
 
-struct Stream {
-  uint64_t seed, event, block;
-  uint64_t buf[4];
-  int pos;
-  __device__ double next() {
-    if (pos == 4) {
-      buf[0] = block;
-      buf[1] = event;
-      buf[2] = 0;
-      buf[3] = 0;
-      philox4x64(buf, seed, 0);
-      ++block;
-      pos = 0;
-    }
-    const uint64_t r = buf[pos++];
-    return (double(r >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-  }
-};
-
 constexpr double kPi = 3.14159265358979323846;
 
 // The bracket of the P-wave decay rate (Eq. 4) times 9 / (32 pi).
-__device__ double pwave_value(double ctl, double ctk, double phi, const double* c) {
+__device__ __noinline__ double pwave_value(double ctl, double ctk, double phi, const double* c) {
   const double FL = c[0], S3 = c[1], S4 = c[2], S5 = c[3], AFB = c[4], S7 = c[5], S8 = c[6], S9 = c[7];
   const double sl2 = 1.0 - ctl * ctl, sk2 = 1.0 - ctk * ctk;
   const double sl = sqrt(sl2), sk = sqrt(sk2);
@@ -104,55 +85,67 @@ __device__ float pwave_value_f32(double ctl, double ctk, double phi, const float
   return float(9.0 / (32.0 * kPi)) * v;
 }
 
-// Draws the dimensions of one leaf into x (user order); false if the draw
-// hit the attempt cap.
-__device__ bool draw_leaf(const GenPlan& G, const GenNode& nd, const double* th, Stream& s, double* x) {
+// Waves per SIMD the generation kernels are built for (a register budget of
+// 512 / kGenWaves per lane).
+constexpr int kGenWaves = 4;
+
+// Per workgroup: the step program, each node's constants at the point, and
+// where each user dimension is stored.
+constexpr int kGenNodeK = 12;
+struct GenShared {
+  GenStep step[kMaxGenSteps];
+  double k[UML_MAX_NODES][kGenNodeK];
+  float kf[UML_MAX_NODES][8];  // P-wave: the coefficients in FP32
+  int dim[UML_MAX_NODES][3];   // leaves: user dimensions
+  int order[UML_MAX_NODES];    // Chebyshev: number of coefficients
+  void* col[UML_MAX_DIMS];
+  double lo[UML_MAX_DIMS], hi[UML_MAX_DIMS];
+};
+
+// A node's parameter-only constants (the same values each draw used to form
+// for itself):
+//   sum          {f}
+//   Gaussian     {mu, sigma, lo, hi}
+//   exponential  {lambda, lo, hi, L = hi - lo, expm1(lambda L)}
+//   Chebyshev    {lo, hi, L, envelope 1 + sum |c_j|, c_1 .. c_k}
+//   P-wave       {c_0 .. c_7, envelope}, and the coefficients in FP32
+__device__ void node_constants(const GenPlan& G, const GenNode& nd, const double* __restrict__ th, double* K,
+                               float* KF) {
   switch (nd.kind) {
+    case UML_SUM:
+      K[0] = th[nd.par[0]];
+      break;
     case UML_GAUSS: {
       const int d = nd.dim[0];
-      const double lo = G.lo[d], hi = G.hi[d], mu = th[nd.par[0]], sg = th[nd.par[1]];
-      for (int a = 0; a < kGenCap; ++a) {
-        const double u1 = s.next(), u2 = s.next();
-        const double v = mu + sg * (sqrt(-2.0 * log(u1)) * cos(2.0 * kPi * u2));
-        if (v >= lo && v <= hi) {
-          x[d] = v;
-          return true;
-        }
-      }
-      x[d] = lo;
-      return false;
+      K[0] = th[nd.par[0]];
+      K[1] = th[nd.par[1]];
+      K[2] = G.lo[d];
+      K[3] = G.hi[d];
+      break;
     }
     case UML_EXP: {
       const int d = nd.dim[0];
       const double lo = G.lo[d], hi = G.hi[d], lam = th[nd.par[0]], L = hi - lo;
-      const double u = s.next();
-      const double v = lam == 0.0 ? lo + u * L : lo + log1p(u * expm1(lam * L)) / lam;
-      x[d] = v < lo ? lo : (v > hi ? hi : v);
-      return true;
+      K[0] = lam;
+      K[1] = lo;
+      K[2] = hi;
+      K[3] = L;
+      K[4] = expm1(lam * L);
+      break;
     }
     case UML_CHEB: {
-      const int d = nd.dim[0], k = nd.npar;
-      const double lo = G.lo[d], hi = G.hi[d], L = hi - lo;
+      const int d = nd.dim[0];
+      const double lo = G.lo[d], hi = G.hi[d];
       double env = 1.0;
-      for (int j = 0; j < k; ++j) env += fabs(th[nd.par[j]]);
-      for (int a = 0; a < kGenCap; ++a) {
-        const double u1 = s.next(), u2 = s.next();
-        const double v = lo + u1 * L;
-        const double t = (2.0 * v - lo - hi) / L;
-        double tm = 1.0, tj = t, val = 1.0;
-        for (int j = 1; j <= k; ++j) {
-          val += th[nd.par[j - 1]] * tj;
-          const double tn = 2.0 * t * tj - tm;
-          tm = tj;
-          tj = tn;
-        }
-        if (u2 * env <= val) {
-          x[d] = v;
-          return true;
-        }
+      for (int j = 0; j < nd.npar; ++j) {
+        env += fabs(th[nd.par[j]]);
+        K[4 + j] = th[nd.par[j]];
       }
-      x[d] = lo;
-      return false;
+      K[0] = lo;
+      K[1] = hi;
+      K[2] = hi - lo;
+      K[3] = env;
+      break;
     }
     case UML_PWAVE: {
       double c[8];
@@ -161,31 +154,31 @@ __device__ bool draw_leaf(const GenPlan& G, const GenNode& nd, const double* th,
                    4.0 / 3.0 * fabs(c[4]);
       for (int k = 1; k < 8; ++k)
         if (k != 4) env += fabs(c[k]);
-      env *= 9.0 / (32.0 * kPi);
-      // The decision u4 env <= value is taken from the FP32 value when the two
-      // sides differ by more than 1e-4 env (fifty times its error bound), and
-      // from the FP64 value otherwise, so it is always the FP64 decision.
-      float cf[8];
-      for (int k = 0; k < 8; ++k) cf[k] = float(c[k]);
-      const float margin = float(1e-4 * env);
-      for (int a = 0; a < kGenCap; ++a) {
-        const double u1 = s.next(), u2 = s.next(), u3 = s.next(), u4 = s.next();
-        const double ctl = 2.0 * u1 - 1.0, ctk = 2.0 * u2 - 1.0, phi = kPi * (2.0 * u3 - 1.0);
-        const double lhs = u4 * env;
-        const float gap = float(lhs) - pwave_value_f32(ctl, ctk, phi, cf);
-        const bool accept = gap > margin ? false : gap < -margin ? true : lhs <= pwave_value(ctl, ctk, phi, c);
-        if (accept) {
-          x[nd.dim[0]] = ctl;
-          x[nd.dim[1]] = ctk;
-          x[nd.dim[2]] = phi;
-          return true;
-        }
+      for (int k = 0; k < 8; ++k) {
+        K[k] = c[k];
+        KF[k] = float(c[k]);
       }
-      for (int k = 0; k < 3; ++k) x[nd.dim[k]] = G.lo[nd.dim[k]];
-      return false;
+      K[8] = env * (9.0 / (32.0 * kPi));
+      break;
     }
   }
-  return false;
+}
+
+// Lane t: step t, node t and user dimension t of the workgroup's tables.
+__device__ void gen_setup(GenShared& S, const GenPlan& G, const double* __restrict__ theta, const GenOut& out) {
+  const int t = threadIdx.x;
+  if (t < G.nstep) S.step[t] = G.step[t];
+  if (t < G.nnode) {
+    const GenNode& nd = G.node[t];
+    node_constants(G, nd, theta, S.k[t], S.kf[t]);
+    for (int k = 0; k < 3; ++k) S.dim[t][k] = nd.dim[k];
+    S.order[t] = nd.npar;
+  }
+  if (t < G.ndim) {
+    S.col[t] = out.col[G.col_of_user[t]];
+    S.lo[t] = G.lo[t];
+    S.hi[t] = G.hi[t];
+  }
 }
 
 template <class T>
@@ -203,76 +196,192 @@ __device__ __forceinline__ float to_storage<float>(double v, double lo, double h
   return f;
 }
 
-// Event i of pseudo-experiment `seed` at theta, stored into out.
 template <class T>
-__device__ void draw_event(const GenPlan& G, const double* __restrict__ theta, uint64_t seed, int64_t i,
-                           const GenOut& out) {
-  double th[UML_MAX_PARAMS];
-  for (int k = 0; k < G.npar; ++k) th[k] = theta[k];
-  double x[UML_MAX_DIMS];
-  for (int d = 0; d < G.ndim; ++d) x[d] = G.lo[d];
-  Stream s{seed, uint64_t(i), 0, {0, 0, 0, 0}, 4};
-  // depth-first walk with an explicit stack (children pushed in reverse,
-  // so they are drawn in order)
-  int stack[UML_MAX_NODES];
-  int top = 0;
-  stack[top++] = G.root;
+__device__ __forceinline__ void store(const GenShared& S, int d, int64_t i, double v) {
+  static_cast<T*>(S.col[d])[i] = to_storage<T>(v, S.lo[d], S.hi[d]);
+}
+
+__device__ __forceinline__ double unit(uint64_t r) {
+  return (double(r >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+// Word idx (0..7) of the two-block window w, by selects (no indexed
+// registers).
+__device__ __forceinline__ uint64_t pick(const uint64_t (&w)[8], int idx) {
+  uint64_t r = w[0];
+#pragma unroll
+  for (int t = 1; t < 8; ++t) r = idx == t ? w[t] : r;
+  return r;
+}
+
+// Events [b0, b1) of pseudo-experiment `seed`, drawn by one wave.  A lane
+// advances its event by one step per pass: a sum's choice or one attempt
+// of a leaf.  The stream words the step needs are taken from a window of
+// two Philox blocks, the next block drawn at the top of the pass when the
+// window runs short, so every lane that needs one computes it together.  A
+// lane whose event is complete takes the next event of the range, so lanes
+// stay busy until the range runs out whatever their accept-reject luck.
+// Each event still reads only its own stream in its own order.
+template <class T>
+__device__ __forceinline__ void gen_range(const GenShared& S, int root, uint64_t seed, int64_t b0, int64_t b1,
+                          unsigned int* bad) {
+  const int lane = threadIdx.x & 63;
+  int64_t pool = b0;  // the next event not yet taken (the same in every lane)
+  int64_t i = 0;
+  int st = -1, a = 0, pos = 0, nb = 0;
   bool ok = true;
-  while (top > 0) {
-    const GenNode& nd = G.node[stack[--top]];
-    if (nd.kind == UML_SUM) {
-      const double u = s.next();
-      stack[top++] = nd.child[u < th[nd.par[0]] ? 0 : 1];
-    } else if (nd.kind == UML_PROD) {
-      for (int c = nd.nchild - 1; c >= 0; --c) stack[top++] = nd.child[c];
-    } else {
-      ok &= draw_leaf(G, nd, th, s, x);
+  uint64_t blk = 0;
+  uint64_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  while (true) {
+    const bool want = st < 0;
+    const uint64_t m = __ballot(want);
+    if (want) {
+      const int64_t j = pool + __popcll(m & ((1ull << lane) - 1));
+      if (j < b1) {
+        i = j;
+        st = root;
+        a = 0;
+        ok = true;
+        blk = 0;
+        nb = 0;
+        pos = 0;
+      }
+    }
+    pool += __popcll(m);
+    if (!__any(st >= 0)) break;
+    if (st < 0) continue;
+    const GenStep P = S.step[st];
+    const double* K = S.k[P.node];
+    const int need = P.kind == UML_PWAVE ? 4 : (P.kind == UML_GAUSS || P.kind == UML_CHEB) ? 2 : 1;
+    if (4 * nb - pos < need) {  // the event's next block: counters (block, event, 0, 0), key (seed, 0)
+      uint64_t x[4] = {blk, uint64_t(i), 0, 0};
+      philox4x64(x, seed, 0);
+      ++blk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        w[t] = nb == 0 ? x[t] : w[t];
+        w[4 + t] = nb == 0 ? w[4 + t] : x[t];
+      }
+      ++nb;
+    }
+    double u[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u[t] = unit(pick(w, pos + t));
+    pos += need;
+    if (pos >= 4) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w[t] = w[4 + t];
+      pos -= 4;
+      --nb;
+    }
+    if (P.kind == UML_SUM) {
+      st = u[0] < K[0] ? P.child[0] : P.child[1];
+      continue;
+    }
+    const int* D = S.dim[P.node];
+    bool drawn = false;  // the leaf has its value
+    if (P.kind == UML_GAUSS) {  // Box-Muller, rejected outside the range
+      const double v = K[0] + K[1] * (sqrt(-2.0 * log(u[0])) * cos(2.0 * kPi * u[1]));
+      drawn = v >= K[2] && v <= K[3];
+      if (drawn) store<T>(S, D[0], i, v);
+    } else if (P.kind == UML_EXP) {  // inverse distribution function
+      const double lam = K[0], lo = K[1], hi = K[2], L = K[3];
+      const double v = lam == 0.0 ? lo + u[0] * L : lo + log1p(u[0] * K[4]) / lam;
+      store<T>(S, D[0], i, v < lo ? lo : (v > hi ? hi : v));
+      drawn = true;
+    } else if (P.kind == UML_CHEB) {  // accept-reject under 1 + sum |c_j|
+      const double lo = K[0], hi = K[1], L = K[2];
+      const double v = lo + u[0] * L;
+      const double t = (2.0 * v - lo - hi) / L;
+      double tm = 1.0, tj = t, val = 1.0;
+      const int k = S.order[P.node];
+      for (int j = 1; j <= k; ++j) {
+        val += K[3 + j] * tj;
+        const double tn = 2.0 * t * tj - tm;
+        tm = tj;
+        tj = tn;
+      }
+      drawn = u[1] * K[3] <= val;
+      if (drawn) store<T>(S, D[0], i, v);
+    } else {  // P-wave: accept-reject of uniform angles
+      // The decision u4 env <= value is taken from the FP32 value when the two
+      // sides differ by more than 1e-4 env (fifty times its error bound), and
+      // from the FP64 value otherwise, so it is always the FP64 decision.
+      const double env = K[8];
+      const float margin = float(1e-4 * env);
+      const double ctl = 2.0 * u[0] - 1.0, ctk = 2.0 * u[1] - 1.0, phi = kPi * (2.0 * u[2] - 1.0);
+      const double lhs = u[3] * env;
+      const float gap = float(lhs) - pwave_value_f32(ctl, ctk, phi, S.kf[P.node]);
+      drawn = gap > margin ? false : gap < -margin ? true : lhs <= pwave_value(ctl, ctk, phi, K);
+      if (drawn) {
+        store<T>(S, D[0], i, ctl);
+        store<T>(S, D[1], i, ctk);
+        store<T>(S, D[2], i, phi);
+      }
+    }
+    if (!drawn && ++a == kGenCap) {  // the attempt cap: the leaf's dimensions at their lower ends
+      const int nd = P.kind == UML_PWAVE ? 3 : 1;
+      for (int k = 0; k < nd; ++k) store<T>(S, D[k], i, S.lo[D[k]]);
+      ok = false;
+      drawn = true;
+    }
+    if (drawn) {
+      st = P.next;
+      a = 0;
+      if (st < 0 && !ok) atomicAdd(bad, 1u);
     }
   }
-  if (!ok) atomicAdd(out.bad, 1u);
-  for (int d = 0; d < G.ndim; ++d)
-    static_cast<T*>(out.col[G.col_of_user[d]])[i] = to_storage<T>(x[d], G.lo[d], G.hi[d]);
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void generate_kernel(const GenPlan* __restrict__ plan,
-                                                       const double* __restrict__ theta, uint64_t seed,
-                                                       const GenOut out) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < out.n) draw_event<T>(*plan, theta, seed, i, out);
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kGenWaves))) void generate_kernel(const GenPlan* __restrict__ plan,
+                                                      const double* __restrict__ theta, uint64_t seed,
+                                                      const GenOut out, int64_t block) {
+  __shared__ GenShared S;
+  gen_setup(S, *plan, theta, out);
+  __syncthreads();
+  const int64_t b0 = int64_t(blockIdx.x) * block;
+  const int64_t b1 = b0 + block < out.n ? b0 + block : out.n;
+  gen_range<T>(S, plan->root_step, seed, b0, b1, out.bad);
 }
 
-// Many pseudo-experiments at once: the map names (job, block of 256 events)
-// for each workgroup.
+// Many pseudo-experiments at once: the map names (job, block of `block`
+// events) for each workgroup.
 template <class T>
-__global__ __launch_bounds__(256) void generate_batch_kernel(const GenPlan* __restrict__ plan,
-                                                             const GenJob* __restrict__ jobs,
-                                                             const int2* __restrict__ map) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kGenWaves))) void generate_batch_kernel(const GenPlan* __restrict__ plan,
+                                                            const GenJob* __restrict__ jobs,
+                                                            const int2* __restrict__ map, int64_t block) {
+  __shared__ GenShared S;
   const int2 t = map[blockIdx.x];
   const GenJob& J = jobs[t.x];
-  const int64_t i = int64_t(t.y) * 256 + threadIdx.x;
-  if (i < J.out.n) draw_event<T>(*plan, J.theta, J.seed, i, J.out);
+  gen_setup(S, *plan, J.theta, J.out);
+  __syncthreads();
+  const int64_t b0 = int64_t(t.y) * block;
+  const int64_t b1 = b0 + block < J.out.n ? b0 + block : J.out.n;
+  gen_range<T>(S, plan->root_step, J.seed, b0, b1, J.out.bad);
 }
 
 }  // namespace
 
 void launch_generate_batch(const GenPlan* d_plan, const GenJob* d_jobs, const int2* d_map, int n_map,
-                           int precision, hipStream_t s) {
+                           int64_t block, int precision, hipStream_t s) {
   if (n_map <= 0) return;
   if (precision == UML_MIXED)
-    hipLaunchKernelGGL(generate_batch_kernel<float>, dim3(n_map), dim3(256), 0, s, d_plan, d_jobs, d_map);
+    hipLaunchKernelGGL(generate_batch_kernel<float>, dim3(n_map), dim3(64), 0, s, d_plan, d_jobs, d_map, block);
   else
-    hipLaunchKernelGGL(generate_batch_kernel<double>, dim3(n_map), dim3(256), 0, s, d_plan, d_jobs, d_map);
+    hipLaunchKernelGGL(generate_batch_kernel<double>, dim3(n_map), dim3(64), 0, s, d_plan, d_jobs, d_map,
+                       block);
 }
 
 void launch_generate(const GenPlan* d_plan, const double* d_theta, uint64_t seed, const GenOut& out,
                      int precision, hipStream_t s) {
   if (out.n <= 0) return;
-  const unsigned blocks = unsigned((out.n + 255) / 256);
+  const int64_t block = gen_block_events(out.n);
+  const unsigned blocks = unsigned((out.n + block - 1) / block);
   if (precision == UML_MIXED)
-    hipLaunchKernelGGL(generate_kernel<float>, dim3(blocks), dim3(256), 0, s, d_plan, d_theta, seed, out);
+    hipLaunchKernelGGL(generate_kernel<float>, dim3(blocks), dim3(64), 0, s, d_plan, d_theta, seed, out, block);
   else
-    hipLaunchKernelGGL(generate_kernel<double>, dim3(blocks), dim3(256), 0, s, d_plan, d_theta, seed, out);
+    hipLaunchKernelGGL(generate_kernel<double>, dim3(blocks), dim3(64), 0, s, d_plan, d_theta, seed, out, block);
 }
 
 }  // namespace uml

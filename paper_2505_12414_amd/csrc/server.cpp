@@ -228,6 +228,7 @@ struct uml_server {
   int2* h_hmap = nullptr;
   int2* d_hmap = nullptr;
   int hmap_cap = 0;
+  int gmap_cap = 0;  // generation map entries
   double* h_hsums = nullptr;
   double* d_hsums = nullptr;
   unsigned int* d_genbad = nullptr;  // per slot: events that failed to draw
@@ -309,6 +310,10 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
   UML_HIP_CHECK(S->up.reset(S->stream));
   UML_HIP_CHECK(hipMemsetAsync(S->d_genbad, 0, sizeof(unsigned int) * ns, S->stream));
   int n_gen = 0, n_gmap = 0;  // requests drawn on the device, in one batched launch
+  int64_t gen_total = 0;
+  for (const auto& it : in)
+    if (it.req.generate) gen_total += it.req.n;
+  const int64_t gblock = gen_block_events(gen_total);
   for (auto& it : in) {
     Slot& sl = S->slots[it.slot];
     sl.off = it.off;
@@ -332,8 +337,8 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
       if (!S->up.put(sl.data.d_out, H.gen_theta, sizeof(double) * UML_MAX_PARAMS))
         return set_error(UML_E_INVALID, "server: upload staging full");
       S->h_genjobs[n_gen] = GenJob{gen_out(&sl.data, S->d_genbad + it.slot), sl.data.d_out, sl.req.seed};
-      for (int64_t b = 0; b * 256 < sl.req.n; ++b) {
-        if (n_gmap >= S->hmap_cap) return set_error(UML_E_INVALID, "server: generation map full");
+      for (int64_t b = 0; b * gblock < sl.req.n; ++b) {
+        if (n_gmap >= S->gmap_cap) return set_error(UML_E_INVALID, "server: generation map full");
         S->h_genmap[n_gmap++] = make_int2(n_gen, int(b));
       }
       ++n_gen;
@@ -349,7 +354,7 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
                                  S->stream));
     UML_HIP_CHECK(hipMemcpyAsync(S->d_genmap, S->h_genmap, sizeof(int2) * n_gmap, hipMemcpyHostToDevice,
                                  S->stream));
-    launch_generate_batch(m->d_gplan, S->d_genjobs, S->d_genmap, n_gmap, m->plan.precision, S->stream);
+    launch_generate_batch(m->d_gplan, S->d_genjobs, S->d_genmap, n_gmap, gblock, m->plan.precision, S->stream);
     UML_HIP_CHECK(hipGetLastError());
   }
   // every work area initialised, start points included, in one packed upload
@@ -679,6 +684,10 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   // tiles, and the arena holds at most budget / (bytes per event) events
   const int64_t ev_bytes = int64_t(m->plan.ndim) * (m->plan.precision == UML_MIXED ? 4 : 8);
   S->hmap_cap = int(std::min<int64_t>(S->opt.hbm_budget / (256 * ev_bytes) + ns, 1 << 22));
+  // generation map capacity: a batch of T events in blocks of
+  // gen_block_events(T) has at most kGenTargetWaves blocks, or T / 512 if
+  // its blocks are the largest, plus one partial block per request
+  S->gmap_cap = int(std::min<int64_t>(kGenTargetWaves + S->opt.hbm_budget / (512 * ev_bytes) + ns, 1 << 22));
   const int M = hess_sums(m);
   auto fail = [&](hipError_t e, const char* what) {
     free_server_memory(S);
@@ -698,7 +707,7 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   const size_t o_genbad = o_hsums + round256(sizeof(double) * size_t(ns) * M);
   const size_t o_genjobs = o_genbad + round256(sizeof(unsigned int) * ns);
   const size_t o_genmap = o_genjobs + round256(sizeof(GenJob) * ns);
-  e = hipMalloc(&S->state_mem, o_genmap + sizeof(int2) * size_t(S->hmap_cap));
+  e = hipMalloc(&S->state_mem, o_genmap + sizeof(int2) * size_t(S->gmap_cap));
   if (e != hipSuccess) return fail(e, "fit states");
   e = hipMemset(S->state_mem, 0, o_map);
   if (e != hipSuccess) return fail(e, "fit states");
@@ -719,7 +728,7 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genjobs), sizeof(GenJob) * ns, hipHostMallocDefault);
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genmap), sizeof(int2) * size_t(S->hmap_cap),
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_genmap), sizeof(int2) * size_t(S->gmap_cap),
                       hipHostMallocDefault);
   // packed transfers: every piece one admission batch uploads (fit state,
   // two jobs, two parameter vectors per request, their records and padding),
