@@ -16,12 +16,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -195,6 +198,78 @@ struct CapturedGraph {
 
 using namespace uml;
 
+// A few host threads that share a batch's per-fit arithmetic (the start
+// metric at admission, the covariance at retirement) with the worker.  Each
+// call of run() is a job of its own with its own counters: a helper that
+// wakes late finds the job's items taken and does nothing, and run()
+// returns once every item has been done, so the function is never called
+// after run() returns.
+class HostPool {
+ public:
+  explicit HostPool(int helpers) {
+    for (int t = 0; t < helpers; ++t) th_.emplace_back([this] { loop(); });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  // f(0) .. f(n - 1) on the helpers and the calling thread.
+  void run(int n, const std::function<void(int)>& f) {
+    if (th_.empty() || n < 8) {
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    auto job = std::make_shared<Task>();
+    job->f = &f;
+    job->n = n;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = job;
+      ++gen_;
+    }
+    cv_.notify_all();
+    job->work();
+    while (job->done.load(std::memory_order_acquire) < n) std::this_thread::yield();
+  }
+
+ private:
+  struct Task {
+    const std::function<void(int)>* f = nullptr;
+    int n = 0;
+    std::atomic<int> next{0}, done{0};
+    void work() {
+      for (int i; (i = next.fetch_add(1, std::memory_order_relaxed)) < n;) {
+        (*f)(i);
+        done.fetch_add(1, std::memory_order_release);
+      }
+    }
+  };
+  void loop() {
+    uint64_t seen = 0;
+    while (true) {
+      std::shared_ptr<Task> job;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        job = job_;
+      }
+      job->work();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::shared_ptr<Task> job_;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 struct uml_server {
   const uml_model* m = nullptr;
   uml_server_options opt{};
@@ -247,6 +322,10 @@ struct uml_server {
   std::vector<Slot> slots;
   std::vector<Job> jobs;
   std::map<int, CapturedGraph> graphs;  // by grid bucket
+  std::unique_ptr<HostPool> pool;       // per-fit host arithmetic of a batch
+  std::vector<int> batch_rc;            // per fit of a batch: its return code
+  std::vector<std::string> batch_err;   // and its message, if it failed
+  std::vector<uml_fit_result> batch_res;  // per fit of a batch: its result
 };
 
 namespace uml {
@@ -383,6 +462,17 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
   UML_HIP_CHECK(hipMemcpyAsync(S->h_genbad, S->d_genbad, sizeof(unsigned int) * ns, hipMemcpyDeviceToHost,
                                S->stream));
   UML_HIP_CHECK(hipStreamSynchronize(S->stream));
+  // the start metrics, fit by fit on the host threads
+  S->pool->run(nb, [&](int j) {
+    const int i = in[j].slot;
+    const Slot& sl = S->slots[i];
+    SlotHost& H = S->h_slots[i];
+    S->batch_rc[j] = UML_OK;
+    if (sl.req.generate && S->h_genbad[i]) return;
+    fit_state_begin(m, sl.req.start.data(), S->opt.fit, H.fs);
+    S->batch_rc[j] = fit_state_metric(m, S->h_hsums + size_t(j) * M, H.fs, "server");
+    if (S->batch_rc[j] != UML_OK) S->batch_err[j] = uml_last_error();  // this thread's message
+  });
   for (int j = 0; j < nb; ++j) {
     const int i = in[j].slot;
     Slot& sl = S->slots[i];
@@ -399,9 +489,7 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
       push_result(S, r, sl.req);
       continue;
     }
-    fit_state_begin(m, sl.req.start.data(), S->opt.fit, H.fs);
-    rc = fit_state_metric(m, S->h_hsums + size_t(j) * M, H.fs, "server");
-    if (rc != UML_OK) return rc;
+    if (S->batch_rc[j] != UML_OK) return set_error(S->batch_rc[j], S->batch_err[j]);
     if (H.fs.done) {  // P <= 0 at the start point
       uml_fit_result r;
       std::memset(&r, 0, sizeof(r));
@@ -459,13 +547,12 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
                                  S->stream));
   }
   UML_HIP_CHECK(hipStreamSynchronize(S->stream));
-  for (int j = 0; j < nb; ++j)
-    std::memcpy(&S->h_slots[fin[j]].fs, S->h_gst + sizeof(FitState) * j, sizeof(FitState));
-  for (int j = 0; j < nb; ++j) {
-    const int i = fin[j];
-    Slot& sl = S->slots[i];
-    const FitState& F = S->h_slots[i].fs;
-    uml_fit_result r;
+  // the results, fit by fit on the host threads (the device work of
+  // polishing and of counting bad events comes after, in order)
+  S->pool->run(nb, [&](int j) {
+    FitState& F = S->h_slots[fin[j]].fs;
+    std::memcpy(&F, S->h_gst + sizeof(FitState) * j, sizeof(FitState));
+    uml_fit_result& r = S->batch_res[j];
     std::memset(&r, 0, sizeof(r));
     r.n_free = P.nfree;
     r.n_iter = F.n_iter;
@@ -476,7 +563,14 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
       r.nll = INFINITY;
     } else if (!polish) {
       finish_from_sums(m, S->h_hsums + size_t(j) * M, F.theta, S->opt.fit, &r, "server");
-    } else {
+    }
+  });
+  for (int j = 0; j < nb; ++j) {
+    const int i = fin[j];
+    Slot& sl = S->slots[i];
+    const FitState& F = S->h_slots[i].fs;
+    uml_fit_result& r = S->batch_res[j];
+    if (r.status != UML_FIT_PDF_NONPOSITIVE && polish) {
       std::vector<double> theta(F.theta, F.theta + P.npar);
       int rc = finish_fit(m, &sl.data, theta, S->opt.fit, &r, S->stream, "server");
       if (rc != UML_OK) return rc;
@@ -675,6 +769,13 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   const int ns = S->opt.max_slots;
   S->slots.resize(ns);
   S->jobs.resize(ns);
+  S->batch_rc.resize(ns);
+  S->batch_err.resize(ns);
+  S->batch_res.resize(ns);
+  // helpers for the per-fit host arithmetic: up to three, leaving cores to
+  // the caller
+  const int hw = int(std::thread::hardware_concurrency());
+  S->pool = std::make_unique<HostPool>(std::max(0, std::min(3, hw / 2 - 1)));
   // tile map capacity: the arena holds at most budget / (bytes of one tile)
   const DataLayout one = data_layout(m->plan, 1, false);
   const int64_t tile_bytes = int64_t(one.E) * kBlock * (m->plan.precision == UML_MIXED ? 4 : 8);
