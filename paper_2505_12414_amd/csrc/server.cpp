@@ -20,6 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -383,6 +384,24 @@ bool pack_init(Packer& up, const uml_data& d, const DataLayout& L, const double*
          up.zero(w + L.o_out, L.o_part - L.o_out);
 }
 
+// The parts of a new fit state the device reads: all but the rows of V and
+// V0 past the free parameters (the device reads both only at rows and
+// columns below nf).  Less than half of the state's bytes at nf = 17.
+bool pack_fit_state(Packer& up, FitState* d, const FitState& h, int nf) {
+  const size_t o_V = offsetof(FitState, V), o_V0 = offsetof(FitState, V0), o_f = offsetof(FitState, f);
+  const size_t rows = sizeof(double) * UML_MAX_PARAMS * size_t(nf);
+  char* dd = reinterpret_cast<char*>(d);
+  const char* hh = reinterpret_cast<const char*>(&h);
+  if (!up.put(dd, hh, o_V) || !up.put(dd + o_f, hh + o_f, sizeof(FitState) - o_f)) return false;
+  return rows == 0 || (up.put(dd + o_V, hh + o_V, rows) && up.put(dd + o_V0, hh + o_V0, rows));
+}
+
+// What retirement reads of a finished fit state: theta, and the scalars
+// from f on (counts and status).
+constexpr size_t kRetTheta = sizeof(double) * UML_MAX_PARAMS;
+constexpr size_t kRetTail = sizeof(FitState) - offsetof(FitState, f);
+constexpr size_t kRetBytes = kRetTheta + kRetTail;
+
 int admit_batch(uml_server* S, std::vector<Intake>& in) {
   const uml_model* m = S->m;
   const int ns = int(S->slots.size());
@@ -508,7 +527,8 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     J.theta = S->d_fs[i].theta;
     J.out = S->d_fs[i].out;
     S->jobs[i] = J;
-    if (!S->up.put(S->d_fs + i, &H.fs, sizeof(FitState)) || !S->up.put(S->d_jobs + i, &S->jobs[i], sizeof(Job)))
+    if (!pack_fit_state(S->up, S->d_fs + i, H.fs, m->plan.nfree) ||
+        !S->up.put(S->d_jobs + i, &S->jobs[i], sizeof(Job)))
       return set_error(UML_E_INVALID, "server: upload staging full");
     std::lock_guard<std::mutex> lk(S->mu);
     S->active++;
@@ -526,13 +546,19 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
   const Plan& P = m->plan;
   const bool polish = S->opt.fit.polish > 0;
   const int nb = int(fin.size()), M = hess_sums(m);
-  // the finished fit states, collected by one kernel and one copy
-  for (int j = 0; j < nb; ++j)
-    S->h_grecs[j] = PackRec{S->d_fs + fin[j], int64_t(sizeof(FitState)) * j, int64_t(sizeof(FitState))};
-  UML_HIP_CHECK(hipMemcpyAsync(S->d_grecs, S->h_grecs, sizeof(PackRec) * nb, hipMemcpyHostToDevice, S->stream));
-  launch_gather(S->d_grecs, nb, S->d_gst, S->stream);
+  // what is read of the finished fit states, collected by one kernel and
+  // one copy
+  for (int j = 0; j < nb; ++j) {
+    char* f = reinterpret_cast<char*>(S->d_fs + fin[j]);
+    const int64_t o = int64_t(kRetBytes) * j;
+    S->h_grecs[2 * j] = PackRec{f, o, int64_t(kRetTheta)};
+    S->h_grecs[2 * j + 1] = PackRec{f + offsetof(FitState, f), o + int64_t(kRetTheta), int64_t(kRetTail)};
+  }
+  UML_HIP_CHECK(
+      hipMemcpyAsync(S->d_grecs, S->h_grecs, sizeof(PackRec) * 2 * nb, hipMemcpyHostToDevice, S->stream));
+  launch_gather(S->d_grecs, 2 * nb, S->d_gst, S->stream);
   UML_HIP_CHECK(hipGetLastError());
-  UML_HIP_CHECK(hipMemcpyAsync(S->h_gst, S->d_gst, sizeof(FitState) * nb, hipMemcpyDeviceToHost, S->stream));
+  UML_HIP_CHECK(hipMemcpyAsync(S->h_gst, S->d_gst, kRetBytes * nb, hipMemcpyDeviceToHost, S->stream));
   if (!polish) {  // the Hessian pass at each final point, read on the device
     std::vector<uml_data*> ds(nb);
     std::vector<const double*> th(nb);
@@ -550,8 +576,9 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
   // the results, fit by fit on the host threads (the device work of
   // polishing and of counting bad events comes after, in order)
   S->pool->run(nb, [&](int j) {
-    FitState& F = S->h_slots[fin[j]].fs;
-    std::memcpy(&F, S->h_gst + sizeof(FitState) * j, sizeof(FitState));
+    FitState& F = S->h_slots[fin[j]].fs;  // theta and the scalars (the rest is not read)
+    std::memcpy(F.theta, S->h_gst + kRetBytes * j, kRetTheta);
+    std::memcpy(&F.f, S->h_gst + kRetBytes * j + kRetTheta, kRetTail);
     uml_fit_result& r = S->batch_res[j];
     std::memset(&r, 0, sizeof(r));
     r.n_free = P.nfree;
@@ -839,11 +866,11 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->up.h), S->up.cap, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->up.d), S->up.cap);
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_grecs), sizeof(PackRec) * ns, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_grecs), sizeof(PackRec) * ns);
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_grecs), sizeof(PackRec) * 2 * ns, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_grecs), sizeof(PackRec) * 2 * ns);
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_gst), sizeof(FitState) * ns, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_gst), sizeof(FitState) * ns);
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_gst), kRetBytes * ns, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_gst), kRetBytes * ns);
   if (e != hipSuccess) return fail(e, "pinned staging");
   S->arena.init(static_cast<char*>(S->arena_mem), size_t(S->opt.hbm_budget));
   S->d_fs = reinterpret_cast<FitState*>(S->state_mem);
