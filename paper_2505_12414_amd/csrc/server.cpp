@@ -492,6 +492,7 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     S->batch_rc[j] = fit_state_metric(m, S->h_hsums + size_t(j) * M, H.fs, "server");
     if (S->batch_rc[j] != UML_OK) S->batch_err[j] = uml_last_error();  // this thread's message
   });
+  int started = 0;  // fits that begin iterating
   for (int j = 0; j < nb; ++j) {
     const int i = in[j].slot;
     Slot& sl = S->slots[i];
@@ -530,8 +531,11 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     if (!pack_fit_state(S->up, S->d_fs + i, H.fs, m->plan.nfree) ||
         !S->up.put(S->d_jobs + i, &S->jobs[i], sizeof(Job)))
       return set_error(UML_E_INVALID, "server: upload staging full");
+    ++started;
+  }
+  {
     std::lock_guard<std::mutex> lk(S->mu);
-    S->active++;
+    S->active += started;
   }
   UML_HIP_CHECK(S->up.flush(S->stream));  // the fit states and jobs of the admitted fits
   return UML_OK;
@@ -592,6 +596,7 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
       finish_from_sums(m, S->h_hsums + size_t(j) * M, F.theta, S->opt.fit, &r, "server");
     }
   });
+  int64_t freed = 0;  // arena bytes of the retired fits
   for (int j = 0; j < nb; ++j) {
     const int i = fin[j];
     Slot& sl = S->slots[i];
@@ -604,11 +609,20 @@ int retire_batch(uml_server* S, const std::vector<int>& fin) {
     }
     int rc = fill_bad_count(m, &sl.data, &r, S->stream, "server");
     if (rc != UML_OK) return rc;
-    release_slot(S, sl);
-    push_result(S, r, sl.req);
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->active--;
+    S->arena.release(sl.off, sl.req.bytes);
+    sl.used = false;
+    freed += int64_t(sl.req.bytes);
+    r.ticket = sl.req.ticket;
+    r.latency_s = now_s() - sl.req.t_submit;
   }
+  {  // the batch's results, under one lock and one notification
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (int j = 0; j < nb; ++j) S->results.push_back(S->batch_res[j]);
+    S->finished += nb;
+    S->active -= nb;
+    S->resident -= freed;
+  }
+  S->cv_result.notify_all();
   return UML_OK;
 }
 
