@@ -10,7 +10,7 @@ import oracle
 from paper_2505_12414_amd import uml
 from paper_2505_12414_amd import workloads as W
 
-from gpu_common import cheb_desc, exp_desc, gauss_desc, say
+from gpu_common import cheb_desc, exp_desc, gauss_desc, mix_desc, say
 
 pytestmark = pytest.mark.gpu
 
@@ -21,7 +21,24 @@ MODELS = [
     ("gauss", lambda: gauss_desc(mu=5.3, sigma=0.1)),
     ("exp", exp_desc),
     ("cheb4", lambda: cheb_desc((0.1, -0.2, 0.05, 0.1))),
+    ("mix3", lambda: mix_desc(3)),
+    ("mix4", lambda: mix_desc(4)),
+    ("shared_leaf", lambda: shared_leaf_desc()),
 ]
+
+
+def shared_leaf_desc():
+    """f1 G(m) + (1 - f1) (f2 G(m) + (1 - f2) E(m)) with the one Gaussian node
+    under both sums (drawn from either branch)."""
+    return {"dims": [{"name": "m", "lo": 5.0, "hi": 5.6}],
+            "params": [{"name": "mu", "value": 5.28}, {"name": "s", "value": 0.03},
+                       {"name": "lambda", "value": -1.2}, {"name": "f1", "value": 0.35},
+                       {"name": "f2", "value": 0.6}],
+            "nodes": [{"kind": "gauss", "dims": [0], "params": [0, 1]},
+                      {"kind": "exp", "dims": [0], "params": [2]},
+                      {"kind": "sum", "children": [0, 1], "params": [4]},
+                      {"kind": "sum", "children": [0, 2], "params": [3]}],
+            "root": 3}
 
 
 def storage(x64, desc, precision):
@@ -78,6 +95,23 @@ def test_generation_at_1e7_events_sampled():
     idx = np.sort(np.random.default_rng(1).choice(n, 3000, replace=False))
     want = np.stack([om.generate(1, seed, i0=int(i))[0][:, 0] for i in idx], axis=1)
     compare(got[:, idx], storage(want, desc, "mixed"), "mixed", "1e7 sampled")
+
+
+@pytest.mark.parametrize("n", [300_000, 600_000])
+def test_generation_with_several_events_per_lane_sampled(n):
+    """Launches of 3e5 and 6e5 events draw two and four events per lane (the
+    lanes take the next event of their block as each one completes): sampled
+    events still equal the oracle's."""
+    desc = W.angmass4d()
+    um = uml.Model(desc, "fp64")
+    om = oracle.Model(desc)
+    seed = 515
+    say(f"case generate angmass4d n={n} (several events per lane)")
+    got = uml.Data.generate(um, n, seed).download()
+    idx = np.sort(np.random.default_rng(n).choice(n, 1000, replace=False))
+    idx[-1] = n - 1  # the last event of the last, partial block
+    want = np.stack([om.generate(1, seed, i0=int(i))[0][:, 0] for i in idx], axis=1)
+    compare(got[:, idx], want, "fp64", f"{n} sampled")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
