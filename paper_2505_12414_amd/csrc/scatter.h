@@ -27,6 +27,9 @@ struct PackRec {
 void launch_scatter(const PackRec* d_recs, int n, const void* d_staging, hipStream_t s);
 // pieces -> staging; one workgroup per record
 void launch_gather(const PackRec* d_recs, int n, void* d_staging, hipStream_t s);
+// out[i] = the int at base + i * stride, i < n; out may be mapped pinned host
+// memory (its device address), so small results reach the host without a copy.
+void launch_collect_ints(const void* base, int64_t stride, int n, int* out, hipStream_t s);
 
 // The domain check of borrowed event columns: every value of kernel dimension
 // d in [lo[d], hi[d]] and every weight finite; bad counts the violations.

@@ -28,6 +28,12 @@ __global__ __launch_bounds__(256) void gather_kernel(const PackRec* __restrict__
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
+__global__ __launch_bounds__(256) void collect_ints_kernel(const char* __restrict__ base, int64_t stride, int n,
+                                                           int* __restrict__ out) {
+  for (int i = int(blockIdx.x) * 256 + threadIdx.x; i < n; i += int(gridDim.x) * 256)
+    out[i] = *reinterpret_cast<const int*>(base + stride * i);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void check_events_kernel(const CheckArgs a) {
   unsigned int bad = 0;
@@ -59,6 +65,13 @@ void launch_check_events(const CheckArgs& a, hipStream_t s) {
 void launch_scatter(const PackRec* d_recs, int n, const void* d_staging, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(scatter_kernel, dim3(n), dim3(256), 0, s, d_recs, static_cast<const uint64_t*>(d_staging));
+}
+
+void launch_collect_ints(const void* base, int64_t stride, int n, int* out, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+  hipLaunchKernelGGL(collect_ints_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const char*>(base), stride,
+                     n, out);
 }
 
 void launch_gather(const PackRec* d_recs, int n, void* d_staging, hipStream_t s) {

@@ -298,6 +298,7 @@ struct uml_server {
   int map_cap = 0;
   SlotHost* h_slots = nullptr;  // pinned, one per slot
   int* h_done = nullptr;        // pinned, one per slot
+  int* h_done_dev = nullptr;    // its device address (written by a kernel)
   // batched Hessian passes: job tables, tile map, sums (pinned and device)
   HessJob* h_hjobs = nullptr;
   HessJob* d_hjobs = nullptr;
@@ -406,7 +407,6 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
   const uml_model* m = S->m;
   const int ns = int(S->slots.size());
   UML_HIP_CHECK(S->up.reset(S->stream));
-  UML_HIP_CHECK(hipMemsetAsync(S->d_genbad, 0, sizeof(unsigned int) * ns, S->stream));
   int n_gen = 0, n_gmap = 0;  // requests drawn on the device, in one batched launch
   int64_t gen_total = 0;
   for (const auto& it : in)
@@ -447,6 +447,9 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
     if (e != hipSuccess) return set_error(UML_E_HIP, std::string("server upload: ") + hipGetErrorString(e));
   }
   if (n_gen) {  // one launch draws every generated request (their points placed first)
+    // the failure counters cleared by the same packed upload
+    if (!S->up.zero(S->d_genbad, (sizeof(unsigned int) * ns + 7) / 8 * 8))
+      return set_error(UML_E_INVALID, "server: upload staging full");
     UML_HIP_CHECK(S->up.flush(S->stream));
     UML_HIP_CHECK(hipMemcpyAsync(S->d_genjobs, S->h_genjobs, sizeof(GenJob) * n_gen, hipMemcpyHostToDevice,
                                  S->stream));
@@ -478,8 +481,9 @@ int admit_batch(uml_server* S, std::vector<Intake>& in) {
   if (rc != UML_OK) return rc;
   UML_HIP_CHECK(hipMemcpyAsync(S->h_hsums, S->d_hsums, sizeof(double) * nb * M, hipMemcpyDeviceToHost,
                                S->stream));
-  UML_HIP_CHECK(hipMemcpyAsync(S->h_genbad, S->d_genbad, sizeof(unsigned int) * ns, hipMemcpyDeviceToHost,
-                               S->stream));
+  if (n_gen)
+    UML_HIP_CHECK(hipMemcpyAsync(S->h_genbad, S->d_genbad, sizeof(unsigned int) * ns, hipMemcpyDeviceToHost,
+                                 S->stream));
   UML_HIP_CHECK(hipStreamSynchronize(S->stream));
   // the start metrics, fit by fit on the host threads
   S->pool->run(nb, [&](int j) {
@@ -743,9 +747,10 @@ void worker_main(uml_server* S) {
       return;
     }
     hipError_t e = hipGraphLaunch(exec, S->stream);
-    if (e == hipSuccess)
-      e = hipMemcpy2DAsync(S->h_done, sizeof(int), &S->d_fs[0].done, sizeof(FitState), sizeof(int), ns,
-                           hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess) {  // every fit's done flag, written by a kernel straight into pinned memory
+      launch_collect_ints(&S->d_fs[0].done, int64_t(sizeof(FitState)), ns, S->h_done_dev, S->stream);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) {
       fail_worker(S, UML_E_HIP, std::string("server iteration: ") + hipGetErrorString(e));
@@ -855,7 +860,8 @@ int uml_server_create(const uml_model* m, const uml_server_options* opts, uml_se
   if (e != hipSuccess) return fail(e, "fit states");
   e = hipHostMalloc(reinterpret_cast<void**>(&S->h_slots), sizeof(SlotHost) * ns, hipHostMallocDefault);
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_done), sizeof(int) * ns, hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void**>(&S->h_done), sizeof(int) * ns, hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&S->h_done_dev), S->h_done, 0);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&S->h_hjobs), sizeof(HessJob) * ns, hipHostMallocDefault);
   if (e == hipSuccess)
