@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "host.h"
+#include "scatter.h"
 
 using namespace uml;
 
@@ -524,6 +525,19 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
     }
     m->fitws_bytes = bytes;
   }
+  if (m->fitdone_n < n) {  // the done flags' mapped pinned buffer, grown on demand
+    if (m->h_fitdone) (void)hipHostFree(m->h_fitdone);
+    m->h_fitdone = m->h_fitdone_dev = nullptr;
+    m->fitdone_n = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&m->h_fitdone), sizeof(int) * n, hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&m->h_fitdone_dev), m->h_fitdone, 0);
+    if (e != hipSuccess) {
+      if (m->h_fitdone) (void)hipHostFree(m->h_fitdone);
+      m->h_fitdone = m->h_fitdone_dev = nullptr;
+      return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
+    }
+    m->fitdone_n = n;
+  }
   char* base = static_cast<char*>(m->d_fitws);
   FitState* d_fs = reinterpret_cast<FitState*>(base + o_fs);
   Job* d_jobs = reinterpret_cast<Job*>(base + o_job);
@@ -547,7 +561,7 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
   UML_HIP_CHECK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
   if (!map.empty())
     UML_HIP_CHECK(hipMemcpyAsync(d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice, s));
-  std::vector<int> done(n, 0);
+  const int* done = m->h_fitdone;
   int launches = 0, since_poll = 0, poll_every = 2;
   const int max_launches = std::max(1, o.max_iter) * 64 + 64;
   while (!map.empty() && launches < max_launches) {
@@ -564,8 +578,8 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
     if (++since_poll < poll_every) continue;
     since_poll = 0;
     poll_every = std::min(poll_every * 2, 16);
-    UML_HIP_CHECK(hipMemcpy2DAsync(done.data(), sizeof(int), &d_fs[0].done, sizeof(FitState),
-                                   sizeof(int), n, hipMemcpyDeviceToHost, s));
+    launch_collect_ints(&d_fs[0].done, int64_t(sizeof(FitState)), n, m->h_fitdone_dev, s);
+    UML_HIP_CHECK(hipGetLastError());
     UML_HIP_CHECK(hipStreamSynchronize(s));
     std::vector<int> still;
     for (int i : live)

@@ -24,6 +24,11 @@ struct uml_model {
   // grown on demand and kept until the model is destroyed
   mutable void* d_fitws = nullptr;
   mutable size_t fitws_bytes = 0;
+  // the fits' done flags, written by a kernel into mapped pinned memory
+  // (host address and device address), grown on demand
+  mutable int* h_fitdone = nullptr;
+  mutable int* h_fitdone_dev = nullptr;
+  mutable int fitdone_n = 0;
   uml::GenPlan gplan;                // the model tree for generation
   uml::GenPlan* d_gplan = nullptr;   // device copy
 };
