@@ -457,6 +457,7 @@ void uml_model_destroy(uml_model* m) {
   if (m->d_hplan) (void)hipFree(m->d_hplan);
   if (m->d_fitws) (void)hipFree(m->d_fitws);
   if (m->h_fitdone) (void)hipHostFree(m->h_fitdone);
+  if (m->h_fitstage) (void)hipHostFree(m->h_fitstage);
   if (m->d_gplan) (void)hipFree(m->d_gplan);
   delete m;
 }

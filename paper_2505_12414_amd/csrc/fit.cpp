@@ -514,13 +514,20 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
   const size_t o_fs = 0, o_job = (sizeof(FitState) * n + 255) / 256 * 256;
   const size_t o_map = o_job + (sizeof(Job) * n + 255) / 256 * 256;
   const size_t bytes = o_map + sizeof(int2) * std::max(total_tiles, 1);
-  if (m->fitws_bytes < bytes) {  // the model's fit workspace, grown on demand
+  if (m->fitws_bytes < bytes) {  // the model's fit workspace and its staging, grown on demand
     if (m->d_fitws) (void)hipFree(m->d_fitws);
+    if (m->h_fitstage) (void)hipHostFree(m->h_fitstage);
     m->d_fitws = nullptr;
+    m->h_fitstage = nullptr;
     m->fitws_bytes = 0;
     hipError_t e = hipMalloc(&m->d_fitws, bytes);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&m->h_fitstage), bytes, hipHostMallocDefault);
     if (e != hipSuccess) {
+      if (m->d_fitws) (void)hipFree(m->d_fitws);
+      if (m->h_fitstage) (void)hipHostFree(m->h_fitstage);
       m->d_fitws = nullptr;
+      m->h_fitstage = nullptr;
       return set_error(UML_E_NOMEM, std::string(fn) + ": " + hipGetErrorString(e));
     }
     m->fitws_bytes = bytes;
@@ -557,10 +564,12 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
   };
   std::vector<int2> map;
   build_map(map);
-  UML_HIP_CHECK(hipMemcpyAsync(d_fs, fs.data(), sizeof(FitState) * n, hipMemcpyHostToDevice, s));
-  UML_HIP_CHECK(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(Job) * n, hipMemcpyHostToDevice, s));
-  if (!map.empty())
-    UML_HIP_CHECK(hipMemcpyAsync(d_map, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice, s));
+  // fit states, jobs and map in one copy from the pinned staging (same layout)
+  char* stage = m->h_fitstage;
+  std::memcpy(stage + o_fs, fs.data(), sizeof(FitState) * n);
+  std::memcpy(stage + o_job, jobs.data(), sizeof(Job) * n);
+  if (!map.empty()) std::memcpy(stage + o_map, map.data(), sizeof(int2) * map.size());
+  UML_HIP_CHECK(hipMemcpyAsync(base, stage, o_map + sizeof(int2) * map.size(), hipMemcpyHostToDevice, s));
   const int* done = m->h_fitdone;
   int launches = 0, since_poll = 0, poll_every = 2;
   const int max_launches = std::max(1, o.max_iter) * 64 + 64;
@@ -587,14 +596,16 @@ int fit_batch_impl(const uml_model* m, const uml_data* const* ds, int n, const d
     if (still.size() != live.size()) {
       live.swap(still);
       build_map(map);
-      if (!map.empty())
-        UML_HIP_CHECK(hipMemcpyAsync(d_map, map.data(), sizeof(int2) * map.size(),
-                                     hipMemcpyHostToDevice, s));
+      if (!map.empty()) {  // (the staging's earlier copies have completed: the poll waited)
+        std::memcpy(stage + o_map, map.data(), sizeof(int2) * map.size());
+        UML_HIP_CHECK(hipMemcpyAsync(d_map, stage + o_map, sizeof(int2) * map.size(), hipMemcpyHostToDevice, s));
+      }
       poll_every = 2;
     }
   }
-  UML_HIP_CHECK(hipMemcpyAsync(fs.data(), d_fs, sizeof(FitState) * n, hipMemcpyDeviceToHost, s));
+  UML_HIP_CHECK(hipMemcpyAsync(stage + o_fs, d_fs, sizeof(FitState) * n, hipMemcpyDeviceToHost, s));
   UML_HIP_CHECK(hipStreamSynchronize(s));
+  std::memcpy(fs.data(), stage + o_fs, sizeof(FitState) * n);
   for (int i = 0; i < n; ++i) {
     FitState& F = fs[i];
     uml_fit_result& r = out[i];

@@ -29,6 +29,8 @@ struct uml_model {
   mutable int* h_fitdone = nullptr;
   mutable int* h_fitdone_dev = nullptr;
   mutable int fitdone_n = 0;
+  // pinned staging in the layout of the fit workspace, grown with it
+  mutable char* h_fitstage = nullptr;
   uml::GenPlan gplan;                // the model tree for generation
   uml::GenPlan* d_gplan = nullptr;   // device copy
 };
