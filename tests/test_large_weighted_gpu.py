@@ -2,7 +2,8 @@
 weighted fits in FP64 and in mixed precision, with the covariance from the
 Hessian pass, against the oracle.  The oracle's own minimum is reached from
 the FP64 fit's point by one Newton step with the oracle's gradient and
-Hessian there (exact to second order at that distance), and the oracle's
+Hessian there (exact to second order at that distance; the step is reported
+and bounded at 1e-3 sigma), and the oracle's
 uncertainties are sqrt(diag H^-1) at that point, or with the sandwich
 covariance H^-1 W2 H^-1 of weighted fits."""
 import numpy as np
@@ -48,6 +49,12 @@ def test_weighted_1e7_fits_against_oracle():
     t_or = t64.copy()
     t_or[free] -= C @ g[free]
     s_or = np.sqrt(np.diag(C))
+    # the Newton step, in units of sigma: small, so the second-order step
+    # lands on the oracle's minimum (the neglected third-order term is of
+    # order step^2) and that minimum does not lean on the GPU's point
+    step = np.abs(C @ g[free]) / s_or
+    say(f"  Newton step to the oracle's minimum: max {step.max():.2e} sigma {np.round(step, 8).tolist()}")
+    assert step.max() <= 1e-3
     w2, bad = om.w2(x.astype(np.float64), t64, w.astype(np.float64))
     assert bad == 0
     s_sw = np.sqrt(np.diag(C @ w2[np.ix_(free, free)] @ C))
