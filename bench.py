@@ -691,7 +691,8 @@ def main():
     ap.add_argument("--loop-fits", type=int, default=5000,
                     help="requests of the same stream run through the per-fit loop")
     ap.add_argument("--rate", type=float, default=500.0, help="open-loop arrival rate, fits/s")
-    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=512,
+                    help="server fit slots (512: about 140 MB resident in the toy study)")
     ap.add_argument("--budget-mb", type=int, default=256, help="server device-memory budget")
     ap.add_argument("--pull-fits", type=int, default=200,
                     help="host events only: independently generated toys for the pulls")
